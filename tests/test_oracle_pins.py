@@ -1,0 +1,385 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix (no GPU).
+
+Each test names the passage it follows.  None of them re-types the oracle's formula: they
+use closed forms, invariants, library conversions, published test vectors and brute
+force on tiny inputs, chosen so that a dropped term, a wrong sign or index, or p(t_m)
+used in place of p(t_{m+1}) fails at least one of them.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2508_17655_amd import instances
+
+
+# --------------------------------------------------------------------------------------
+# Generator: SplitMix64 (Steele, Lea, Flood 2014) and the App. A initial conditions
+# --------------------------------------------------------------------------------------
+SM64_SEED = 1234567
+SM64_FIRST5 = [6457827717110365317, 3203168211198807973, 9817491932198370423, 4593380528125082431,
+               16408922859458223821]
+
+
+def test_splitmix64_published_vector(orc):
+    # the published first five outputs of SplitMix64 seeded with 1234567
+    assert [orc.splitmix64_at(SM64_SEED, k) for k in range(1, 6)] == SM64_FIRST5
+    got = instances.splitmix64(SM64_SEED, np.arange(1, 6, dtype=np.uint64)).tolist()
+    assert got == SM64_FIRST5
+
+
+def test_init_state_matches_definition(orc):
+    # App. A: x_i(0) uniform in (-0.1, 0.1), y_i(0) = 0; counter (2 r + s) n + i, draw +1
+    n, R, seed = 37, 5, 99
+    x, y = orc.init_state(n, R, seed, orc.INIT_X)
+    assert np.all(y == 0) and np.all(np.abs(x) < 0.1)
+    for r in range(R):
+        k = np.arange(2 * r * n, 2 * r * n + n, dtype=np.uint64) + np.uint64(1)
+        u = (instances.splitmix64(seed, k) >> np.uint64(11)).astype(np.float64) * 2.0**-53
+        np.testing.assert_array_equal(x[r], (-0.1 + 0.2 * u).astype(np.float32))
+    # replica r's start does not depend on the number of replicas
+    x2, _ = orc.init_state(n, 2, seed, orc.INIT_X)
+    np.testing.assert_array_equal(x2, x[:2])
+    # XY mode draws y from the second stream
+    x3, y3 = orc.init_state(n, R, seed, orc.INIT_XY)
+    np.testing.assert_array_equal(x3, x)
+    k = np.arange(n, 2 * n, dtype=np.uint64) + np.uint64(1)
+    u = (instances.splitmix64(seed, k) >> np.uint64(11)).astype(np.float64) * 2.0**-53
+    np.testing.assert_array_equal(y3[0], (-0.1 + 0.2 * u).astype(np.float32))
+    # Sec. IV chaos start: x = +-0.1
+    x4, y4 = orc.init_state(4000, 1, seed, orc.INIT_PM01)
+    assert np.all(np.abs(x4) == np.float32(0.1)) and np.all(y4 == 0)
+    assert 1800 < np.sum(x4 > 0) < 2200
+
+
+# --------------------------------------------------------------------------------------
+# Number formats: OCP E4M3 and bfloat16, against PyTorch's CPU conversions
+# --------------------------------------------------------------------------------------
+def test_e4m3_code_points(orc):
+    # OCP 8-bit FP, E4M3: bias 7, max 448, min normal 2^-6, min subnormal 2^-9, NaN 0x7F
+    assert orc.e4m3_decode(0x38) == 1.0 and orc.e4m3_decode(0xB8) == -1.0
+    assert orc.e4m3_decode(0x7E) == 448.0 and orc.e4m3_decode(0x08) == 2.0**-6
+    assert orc.e4m3_decode(0x01) == 2.0**-9 and orc.e4m3_decode(0x07) == 7 * 2.0**-9
+    assert math.isnan(orc.e4m3_decode(0x7F))
+    codes = [b for b in range(256) if (b & 0x7F) != 0x7F]
+    vals = np.array([orc.e4m3_decode(b) for b in codes], dtype=np.float32)
+    np.testing.assert_array_equal(orc.e4m3_encode(vals), np.array(codes, dtype=np.uint8))
+
+
+def _e4m3_torch(v: np.ndarray) -> np.ndarray:
+    return torch.from_numpy(v.astype(np.float32)).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+
+
+def test_e4m3_rounding_matches_torch(orc):
+    # every E4M3 value, its neighbours one binary32 ulp away and the midpoints between
+    # consecutive values (ties to even), plus random values, all within |v| <= 448
+    pos = np.array(sorted({orc.e4m3_decode(b) for b in range(0x7F)}), dtype=np.float64)
+    mids = (pos[1:] + pos[:-1]) / 2
+    base = np.concatenate([pos, mids]).astype(np.float32)
+    up = np.nextafter(base, np.float32(np.inf))
+    dn = np.nextafter(base, np.float32(-np.inf))
+    rng = np.random.default_rng(0)
+    rnd = np.concatenate([rng.uniform(-1, 1, 200000), rng.uniform(-448, 448, 50000),
+                          np.exp2(rng.uniform(-14, 0, 100000)) * rng.choice([-1, 1], 100000)])
+    v = np.concatenate([base, up, dn, -base, -up, -dn, rnd]).astype(np.float32)
+    v = v[np.abs(v) <= 448]
+    np.testing.assert_array_equal(orc.e4m3_encode(v), _e4m3_torch(v))
+    # the value form agrees with the code form
+    dec = np.array([orc.e4m3_decode(int(b)) for b in orc.e4m3_encode(v[:5000])])
+    np.testing.assert_array_equal(orc.e4m3_round(v[:5000].astype(np.float64)), dec)
+
+
+def test_bf16_rounding_matches_torch(orc):
+    rng = np.random.default_rng(1)
+    v = np.concatenate([rng.uniform(-1, 1, 300000), rng.standard_normal(100000)]).astype(np.float32)
+    # ties: values exactly half-way between bf16 neighbours
+    t = (rng.integers(0, 2**15, 20000).astype(np.uint32) << 16) | np.uint32(0x8000)
+    v = np.concatenate([v, t.view(np.float32)[np.isfinite(t.view(np.float32))]])
+    ref = torch.from_numpy(v).to(torch.bfloat16).float().numpy()
+    np.testing.assert_array_equal(orc.bf16_round(v), ref)
+
+
+# --------------------------------------------------------------------------------------
+# Energy (eq. (1)), cut (Sec. III) and the exhaustive ground state
+# --------------------------------------------------------------------------------------
+def test_energy_closed_forms(orc):
+    rng = np.random.default_rng(2)
+    n = 50
+    s = rng.choice([-1, 1], size=(20, n)).astype(np.int8)
+    # ferromagnet J_ij = 1 (i != j): E = -((sum s)^2 - n)/2
+    J = np.ones((n, n)) - np.eye(n)
+    np.testing.assert_array_equal(orc.energy(J, s), -0.5 * (s.sum(1).astype(float) ** 2 - n))
+    # Mattis J_ij = xi_i xi_j: E = -((xi . s)^2 - n)/2
+    xi = rng.choice([-1.0, 1.0], size=n)
+    J = np.outer(xi, xi) - np.eye(n)
+    np.testing.assert_array_equal(orc.energy(J, s), -0.5 * ((s @ xi) ** 2 - n))
+    # spin-flip symmetry
+    J = instances.dense_gaussian(n, 3).astype(np.float64)
+    np.testing.assert_allclose(orc.energy(J, s), orc.energy(J, -s), rtol=0, atol=1e-12)
+
+
+def test_cut_identity(orc):
+    # cut(s) with weights w = -J counted edge by edge equals -(sum_{i<j} J_ij + E(s))/2
+    rng = np.random.default_rng(4)
+    for J in (instances.dense_pm1(60, 5), instances.erdos_renyi_pm1(80, 0.05, 6)):
+        J = J.astype(np.float64)
+        iu = np.triu_indices(J.shape[0], 1)
+        s = rng.choice([-1, 1], size=(10, J.shape[0])).astype(np.int8)
+        E = orc.energy(J, s)
+        for r in range(10):
+            assert orc.cut_direct(J, s[r]) == -0.5 * (J[iu].sum() + E[r])
+
+
+def _brute_force_python(J):
+    n = J.shape[0]
+    best = math.inf
+    for bits in itertools.product((-1, 1), repeat=n):
+        s = np.array(bits, dtype=float)
+        e = 0.0
+        for i in range(n):
+            for j in range(n):
+                e += J[i, j] * s[i] * s[j]
+        best = min(best, -0.5 * e)
+    return best
+
+
+def test_ground_state_closed_forms(orc):
+    n = 14
+    J = np.ones((n, n)) - np.eye(n)
+    E0, s = orc.ground_state(J)
+    assert E0 == -0.5 * n * (n - 1) and abs(int(s.sum())) == n
+    for n in (13, 14):  # complete antiferromagnet: E = ((sum s)^2 - n)/2
+        E0, _ = orc.ground_state(-(np.ones((n, n)) - np.eye(n)))
+        assert E0 == (0.5 * (1 - n) if n % 2 else -0.5 * n)
+    rng = np.random.default_rng(7)
+    xi = rng.choice([-1.0, 1.0], size=16)
+    E0, s = orc.ground_state(np.outer(xi, xi) - np.eye(16))
+    assert E0 == -0.5 * 16 * 15 and abs(int(s @ xi)) == 16
+    # open chain (a tree, so unfrustrated): E0 = -sum |J_{i,i+1}|
+    n = 18
+    J = np.zeros((n, n))
+    w = rng.choice([-1.0, 1.0], size=n - 1) * rng.integers(1, 4, size=n - 1)
+    for i in range(n - 1):
+        J[i, i + 1] = J[i + 1, i] = w[i]
+    E0, s = orc.ground_state(J)
+    assert E0 == -np.abs(w).sum()
+    assert orc.energy(J, s[None])[0] == E0
+
+
+def test_ground_state_vs_python_enumeration(orc):
+    for seed in range(3):
+        J = instances.dense_gaussian(9, 100 + seed).astype(np.float64)
+        E0, s = orc.ground_state(J)
+        assert abs(E0 - _brute_force_python(J)) < 1e-12
+        assert abs(orc.energy(J, s[None])[0] - E0) < 1e-12
+
+
+# --------------------------------------------------------------------------------------
+# Dynamics, eqs. (3)-(7)
+# --------------------------------------------------------------------------------------
+def _modes_reference(J, c, dt, M, x0, y0):
+    """bSB in the linear regime (no wall contact): every eigenmode k of J obeys the
+    symplectic-Euler recurrence b <- b - (p(t_{m+1}) - c lambda_k) a dt, a <- a + b dt
+    with p(t_{m+1}) = p(t_m) - p(t_m)/(M - m) (eqs. (3), (4), (6), App. A)."""
+    lam, V = np.linalg.eigh(J)
+    a = V.T @ x0
+    b = V.T @ y0
+    p = 1.0
+    out = []
+    for m in range(M):
+        p = p - p / (M - m)
+        b = b - (p - c * lam) * a * dt
+        a = a + b * dt
+        out.append(V @ a)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("mode,tol", [("fp64", 1e-11), ("fp32", 2e-4)])
+def test_bsb_linear_regime_matches_eigenmodes(orc, mode, tol):
+    n, M, dt = 12, 60, 0.7
+    J = instances.dense_gaussian(n, 11).astype(np.float64)
+    c = 0.3 / np.linalg.eigvalsh(J)[-1]
+    rng = np.random.default_rng(3)
+    x0 = (rng.uniform(-1, 1, n) * 1e-6).astype(np.float32)
+    y0 = (rng.uniform(-1, 1, n) * 1e-6).astype(np.float32)
+    ref = _modes_reference(J, c, dt, M, x0.astype(np.float64), y0.astype(np.float64))
+    _, _, _, traj = orc.run(J, orc.BSB, dt=dt, c=c, steps=M, x=x0[None], y=y0[None], mode=mode, record=True)
+    assert np.abs(traj).max() < 1.0  # no wall contact: the linear regime holds
+    err = np.abs(traj[0] - ref).max() / np.abs(ref).max()
+    assert err < tol, err
+
+
+def test_dsb_two_spin_closed_form(orc):
+    # dSB (Sec. VI) on a ferromagnetic pair, constant p = 1, both x > 0: sgn(x) = 1, so
+    # x_{m+1} - (2 - dt^2) x_m + x_{m-1} = c dt^2 (eq. (10) with the coupling as a constant
+    # force), solved by x_m = c + (x_0 - c) cos(m th) + B sin(m th), cos th = 1 - dt^2/2.
+    J = np.array([[0.0, 1.0], [1.0, 0.0]])
+    x0, c, dt, M = 0.05, 0.1, 0.6, 200
+    _, _, _, traj = orc.run(J, orc.DSB, dt=dt, c=c, steps=M, x=np.full((1, 2), x0), y=np.zeros((1, 2)),
+                            schedule=orc.SCHED_CONSTANT, mode="fp64", record=True)
+    th = math.acos(1 - dt * dt / 2)
+    x1 = x0 + (c - x0) * dt * dt
+    B = (x1 - c - (x0 - c) * math.cos(th)) / math.sin(th)
+    m = np.arange(1, M + 1)
+    ref = c + (x0 - c) * np.cos(m * th) + B * np.sin(m * th)
+    assert np.all(traj[0] > 0)
+    np.testing.assert_allclose(traj[0][:, 0], ref, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(traj[0][:, 1], ref, rtol=0, atol=1e-12)
+    # GdSB with a constant schedule keeps p = 1, so it is the same trajectory
+    _, _, _, traj2 = orc.run(J, orc.GDSB, A=0.7, dt=dt, c=c, steps=M, x=np.full((1, 2), x0), y=np.zeros((1, 2)),
+                             schedule=orc.SCHED_CONSTANT, mode="fp64", record=True)
+    np.testing.assert_array_equal(traj, traj2)
+
+
+def test_linear_schedule_closed_form(orc):
+    # eq. (6): the recurrence p <- p - p/(M - m) from p = 1 gives p(t_m) = 1 - m/M
+    n, M = 8, 300
+    J = instances.dense_pm1(n, 1).astype(np.float64)
+    x0, _ = orc.init_state(n, 2, 5)
+    for m_end in (1, 17, 150, 299, 300):
+        _, _, p = orc.run(J, orc.BSB, dt=0.5, c=0.2, steps=M, x=x0, y=np.zeros_like(x0), m_end=m_end, mode="fp64")
+        np.testing.assert_allclose(p, 1 - m_end / M, rtol=0, atol=1e-13)
+
+
+def test_gbsb_control_invariants(orc):
+    # eq. (7) with 0 <= A <= 1 and |x| <= 1 multiplies p each step by a factor in
+    # [1 - r_m, 1 - (1 - A) r_m], so 1 - m/M <= p <= 1; and at the last step (r = 1)
+    # p(t_M) = A x(t_{M-1})^2 p(t_{M-1}).
+    n, M, A = 64, 120, 0.6
+    J = instances.dense_pm1(n, 8).astype(np.float64)
+    c = instances.paper_c(n)
+    x0, y0 = orc.init_state(n, 4, 3, orc.INIT_XY)
+    for m_end in (10, 60, 119):
+        x, y, p = orc.run(J, orc.GBSB, A=A, dt=1.0, c=c, steps=M, x=x0, y=y0, m_end=m_end, mode="fp64")
+        assert np.all(p <= 1 + 1e-15) and np.all(p >= 1 - m_end / M - 1e-13)
+    x, y, p = orc.run(J, orc.GBSB, A=A, dt=1.0, c=c, steps=M, x=x0, y=y0, m_end=M - 1, mode="fp64")
+    _, _, pM = orc.run(J, orc.GBSB, A=A, dt=1.0, c=c, steps=M, x=x, y=y, p=p, m_begin=M - 1, m_end=M, mode="fp64")
+    # p - (1 - A x^2) p cancels to A x^2 p up to a few ulps of p
+    assert np.all(np.abs(pM - A * x * x * p) <= 4 * np.finfo(np.float64).eps * p)
+    assert np.abs(pM - A * x * x * p).max() < 1e-3 * np.abs(A * x * x * p).max()
+    # the control leaves p untouched where it should: A = 0 is bSB exactly (Sec. II)
+    for mode in ("fp64", "fp32"):
+        a = orc.run(J, orc.GBSB, A=0.0, dt=1.0, c=c, steps=M, x=x0, y=y0, mode=mode)
+        b = orc.run(J, orc.BSB, A=0.9, dt=1.0, c=c, steps=M, x=x0, y=y0, mode=mode)
+        for u, v in zip(a, b):
+            np.testing.assert_array_equal(u, v)
+
+
+@pytest.mark.parametrize("variant", ["bsb", "dsb", "gbsb", "gdsb"])
+def test_wall_invariant(orc, variant):
+    # eq. (5): |x| <= 1 after every step, and y = 0 wherever x sits on a wall
+    n, M = 100, 300
+    J = instances.dense_pm1(n, 12).astype(np.float64)
+    x0, y0 = orc.init_state(n, 3, 4)
+    for mode in ("fp64", "fp32"):
+        x, y, p, traj = orc.run(J, orc.VARIANTS[variant], A=0.3, dt=1.25, c=instances.paper_c(n), steps=M,
+                                x=x0, y=y0, mode=mode, record=True)
+        assert np.abs(traj).max() <= 1.0
+        assert np.any(np.abs(x) == 1.0)
+        assert np.all(y[np.abs(x) == 1.0] == 0.0)
+
+
+@pytest.mark.parametrize("variant", ["bsb", "dsb", "gbsb", "gdsb"])
+@pytest.mark.parametrize("form", [0, 1, 2])
+def test_flip_and_gauge_symmetry(orc, variant, form):
+    # h = 0: the dynamics commutes with x -> -x and with the gauge map J -> D J D, x -> D x
+    # (D = diag(+-1)); both are exact in floating point (sign-symmetric rounding).
+    n, M = 40, 150
+    J = instances.dense_pm1(n, 21).astype(np.float64)
+    x0, y0 = orc.init_state(n, 2, 9, orc.INIT_XY)
+    d = np.where(np.random.default_rng(5).random(n) < 0.5, -1.0, 1.0)
+    kw = dict(A=0.4, dt=1.1, c=instances.paper_c(n), steps=M, form=form)
+    for mode in ("fp64", "fp32"):
+        v = orc.VARIANTS[variant]
+        x, y, p = orc.run(J, v, x=x0, y=y0, mode=mode, **kw)
+        xf, yf, pf = orc.run(J, v, x=-x0, y=-y0, mode=mode, **kw)
+        np.testing.assert_array_equal(xf, -x)
+        np.testing.assert_array_equal(pf, p)
+        xg, yg, pg = orc.run(d[:, None] * J * d[None, :], v, x=x0 * d.astype(np.float32), y=y0 * d.astype(np.float32),
+                             mode=mode, **kw)
+        np.testing.assert_array_equal(xg, x * d)
+        np.testing.assert_array_equal(pg, p)
+
+
+def test_permutation_symmetry_exact_products(orc):
+    # relabelling the spins permutes the trajectory; exact for the sign and E4M3 products
+    n, M = 48, 200
+    J = instances.dense_pm1(n, 31).astype(np.float64)
+    x0, y0 = orc.init_state(n, 2, 1)
+    perm = np.random.default_rng(8).permutation(n)
+    for variant, form in ((orc.DSB, 0), (orc.GDSB, 0), (orc.GBSB, orc.FORM_E4M3)):
+        x, _, _ = orc.run(J, variant, A=0.3, dt=1.25, c=0.1, steps=M, x=x0, y=y0, form=form, mode="fp32")
+        xp, _, _ = orc.run(J[np.ix_(perm, perm)], variant, A=0.3, dt=1.25, c=0.1, steps=M, x=x0[:, perm],
+                           y=y0[:, perm], form=form, mode="fp32")
+        np.testing.assert_array_equal(xp, x[:, perm])
+
+
+def test_stability_threshold(orc):
+    # App. A, eqs. (11)-(12): with p = 1 and c = 1/lambda_max, symplectic Euler is stable
+    # for dt < 2/sqrt(1 - lambda_min/lambda_max) and the lambda_min mode grows beyond it.
+    n = 40
+    J = instances.dense_pm1(n, 41).astype(np.float64)
+    lam = np.linalg.eigvalsh(J)
+    c = 1.0 / lam[-1]
+    dtc = 2.0 / math.sqrt(1.0 - lam[0] / lam[-1])
+    x0, _ = orc.init_state(n, 1, 2)
+    x0 = x0 * 1e-3
+    y0 = np.zeros_like(x0)
+    _, _, _, tr = orc.run(J, orc.BSB, dt=0.97 * dtc, c=c, steps=3000, x=x0, y=y0, schedule=orc.SCHED_CONSTANT,
+                          mode="fp64", record=True)
+    assert np.abs(tr).max() < 0.05
+    _, _, _, tr = orc.run(J, orc.BSB, dt=1.03 * dtc, c=c, steps=3000, x=x0, y=y0, schedule=orc.SCHED_CONSTANT,
+                          mode="fp64", record=True)
+    assert np.abs(tr).max() == 1.0
+
+
+def test_fp32_mode_tracks_fp64(orc):
+    # One binary32 step from a binary32 state agrees with the binary64 step to a few ulps
+    # (Fig. 2(a): the update is 32-bit floating point); over the first steps the two
+    # trajectories stay within 1e-5 until wall contacts and the unstable modes amplify
+    # the rounding (measured: ~1e-6 at step 10 for N = 200).
+    n = 200
+    J = instances.dense_pm1(n, 51).astype(np.float64)
+    x0, _ = orc.init_state(n, 4, 6)
+    y0 = np.zeros_like(x0)
+    for var in (orc.BSB, orc.GBSB):
+        kw = dict(A=0.2, dt=1.25, c=instances.paper_c(n), steps=2000)
+        x, y, p = orc.run(J, var, x=x0, y=y0, m_end=40, mode="fp64", **kw)
+        x32, y32, p32 = (a.astype(np.float32) for a in (x, y, p))
+        a64 = orc.run(J, var, x=x32, y=y32, p=p32, m_begin=40, m_end=41, mode="fp64", **kw)[0]
+        a32 = orc.run(J, var, x=x32, y=y32, p=p32, m_begin=40, m_end=41, mode="fp32", **kw)[0]
+        assert np.abs(a32 - a64).max() < 1e-6
+        t64 = orc.run(J, var, x=x0, y=y0, m_end=10, mode="fp64", record=True, **kw)[3]
+        t32 = orc.run(J, var, x=x0, y=y0, m_end=10, mode="fp32", record=True, **kw)[3]
+        rel = np.linalg.norm(t32 - t64, axis=2) / np.linalg.norm(t64, axis=2)
+        assert rel.max() < 1e-5
+
+
+def test_gbsb_finds_brute_force_ground_state(orc):
+    # Sec. III: GbSB finds optimal solutions; on tiny instances the optimum is known exactly.
+    hits = 0
+    for seed in range(4):
+        n = 16
+        J = instances.dense_pm1(n, 60 + seed).astype(np.float64)
+        E0, _ = orc.ground_state(J)
+        x0, y0 = orc.init_state(n, 64, seed)
+        x, _, _ = orc.run(J, orc.GBSB, A=0.2, dt=1.25, c=instances.paper_c(n), steps=400, x=x0, y=y0, mode="fp64")
+        E = orc.energy(J, orc.spins(x))
+        assert E.min() >= E0
+        hits += E.min() == E0
+    assert hits >= 3
+
+
+def test_delta_definition(orc):
+    # eq. (8) and Sec. IV: delta(0) = 1e-6 for x2 = x1 +- 2e-6; delta <= 1; delta -> 1/sqrt(2)
+    # for independent random +-1 configurations.
+    rng = np.random.default_rng(9)
+    n = 2000
+    x1 = rng.choice([-0.1, 0.1], n)
+    x2 = x1 + rng.choice([-2e-6, 2e-6], n)
+    assert abs(orc.delta(x1, x2) - 1e-6) < 1e-15
+    assert orc.delta(np.ones(n), -np.ones(n)) == 1.0
+    a, b = rng.choice([-1.0, 1.0], (2, 200000))
+    assert abs(orc.delta(a, b) - 1 / math.sqrt(2)) < 5e-3
