@@ -1,0 +1,189 @@
+/*
+ * gsb.h -- C ABI of libgsb: simulated bifurcation (bSB, dSB) and its generalisation
+ * with individual bifurcation-parameter control (GbSB), for the Ising problem, on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Goto, Hidaka, Tatsumura, "Edge-of-chaos enhanced quantum-inspired algorithm
+ * for combinatorial optimization", arXiv 2508.17655.
+ *   problem      : minimise E = -1/2 sum_ij J_ij s_i s_j, eq. (1), J symmetric, J_ii = 0.
+ *   dynamics     : symplectic-Euler steps, eqs. (3)-(4), perfectly inelastic walls at
+ *                  |x| = 1, eq. (5); bifurcation parameter p from 1 to 0 by eq. (6), or
+ *                  per-variable by eq. (7) with control strength A (GbSB).
+ *   dSB          : J_ij x_j replaced by J_ij sgn(x_j) in eq. (3) (Sec. VI).
+ *   parameters   : c = 1/lambda_max(J), x_i(0) ~ U(-0.1, 0.1), y_i(0) = 0 (App. A).
+ *
+ * Conventions for every entry point:
+ *   - Return value is a gsb_status; GSB_OK (0) on success.  On failure a message is
+ *     available from gsb_last_error() (thread-local, valid until the next call on the
+ *     same thread).  No C++ exception crosses this boundary.
+ *   - Pointers documented as "host" point to caller-owned host memory; the library
+ *     copies what it needs and keeps no reference after the call returns.  Pointers
+ *     documented as "device" point to memory on the current HIP device.
+ *   - A context is used by one host thread at a time.  All device work of a context
+ *     is enqueued on its stream (gsb_set_stream; default: the null stream).  Calls
+ *     that return results to host memory synchronise that stream first.
+ *   - After any error a context can still be destroyed.
+ */
+#ifndef GSB_H
+#define GSB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gsb_ctx gsb_ctx; /* opaque; owns host copies and device buffers */
+
+typedef enum {
+  GSB_OK = 0,
+  GSB_EINVAL = -1,        /* argument out of range / null pointer */
+  GSB_ENOTSYM = -2,       /* J not exactly symmetric (eq. (1) requires J_ij = J_ji) */
+  GSB_EDIAG = -3,         /* nonzero diagonal (eq. (1) requires J_ii = 0) */
+  GSB_ENONFINITE = -4,    /* NaN or infinity in J, h or a state array */
+  GSB_ENOMEM = -5,        /* device or host allocation failed / workspace too small */
+  GSB_EDEVICE = -6,       /* HIP runtime error or a device-side timeout */
+  GSB_ESTATE = -7,        /* call out of order (e.g. gsb_energy before gsb_init) */
+  GSB_EUNSUPPORTED = -8   /* valid request this build does not provide */
+} gsb_status;
+
+/* Variants.  bSB: eqs. (3)-(6).  dSB: bSB with the sign product (Sec. VI).  GbSB: bSB
+ * with eq. (7) (the paper's generalised SB).  GdSB: eq. (7) applied to the dSB sign
+ * product (the extension the paper's outlook, Sec. VII, asks about). */
+typedef enum { GSB_BSB = 0, GSB_DSB = 1, GSB_GBSB = 2, GSB_GDSB = 3 } gsb_variant;
+
+/* Schedules.  LINEAR: p_i(t_0) = 1 and eq. (7) (eq. (6) when A = 0), which reaches 0 at
+ * t_M.  CONSTANT: p_i = 1 throughout (used for the stability analysis of App. A). */
+typedef enum { GSB_SCHED_LINEAR = 0, GSB_SCHED_CONSTANT = 1 } gsb_schedule;
+
+/* Arithmetic of the coupling product sum_j J_ij q_j (eq. (3)).  The update of p, y, x and
+ * the wall is always binary32 (Fig. 2(a) caption).
+ *   FP32   : J and q in binary32 on MFMA, binary32 accumulation.
+ *   BF16X2 : J in bfloat16; continuous q split into hi = bf16(x), lo = bf16(x - hi);
+ *            two MFMA passes, binary32 accumulation.
+ *   FP8    : J and q in OCP E4M3 on MFMA, binary32 accumulation.  Requires J_ij in
+ *            {0, +1, -1}.  Sign operands (dSB, GdSB) are exact, so the product is exact;
+ *            continuous operands (bSB, GbSB) are rounded to E4M3 (nearest even), and the
+ *            product of the rounded values is exact. */
+typedef enum { GSB_PREC_FP32 = 0, GSB_PREC_BF16X2 = 1, GSB_PREC_FP8 = 2 } gsb_precision;
+
+/* Initial conditions (drawn on the device from the run seed with counter-based
+ * SplitMix64, one counter per (replica, stream, spin); replica r's start does not
+ * depend on the replica count).
+ *   X    : x ~ U(-0.1, 0.1), y = 0 (App. A; default).
+ *   XY   : x and y ~ U(-0.1, 0.1).
+ *   PM01 : x = +-0.1 with a random sign, y = 0 (the chaos start of Sec. IV). */
+typedef enum { GSB_INIT_X = 0, GSB_INIT_XY = 1, GSB_INIT_PM01 = 2 } gsb_init_mode;
+
+/* Options for gsb_set / gsb_get. */
+typedef enum {
+  GSB_OPT_C = 0,          /* coupling constant c (default 1/lambda_max, App. A) */
+  GSB_OPT_PRECISION = 1,  /* gsb_precision (default GSB_PREC_FP8 when J is in {0,+-1},
+                             else GSB_PREC_BF16X2) */
+  GSB_OPT_INIT_MODE = 2,  /* gsb_init_mode (default GSB_INIT_X) */
+  GSB_OPT_LAMBDA_MAX = 3, /* read-only: largest eigenvalue of J (binary64) */
+  GSB_OPT_LAMBDA_MIN = 4, /* read-only: smallest eigenvalue of J (binary64) */
+  GSB_OPT_N = 5,          /* read-only: number of spins n */
+  GSB_OPT_STEP = 6,       /* read-only: current step index m of the run */
+  GSB_OPT_REPLICAS = 7,   /* read-only: replicas of the current run */
+  GSB_OPT_DT_STABLE = 8,  /* read-only: eq. (13) time step with D_t = 1.25 */
+  GSB_OPT_N_DYN = 9       /* read-only: spins carried by the dynamics (n, plus 1 with a
+                             field ancilla); the length of one replica in gsb_state */
+} gsb_option;
+
+/* Create a context for the instance (J, h).
+ *   J : host, n*n binary32, row-major.  Must be finite, exactly symmetric, zero diagonal
+ *       (eq. (1)).  Copied.
+ *   h : host, n binary32, or NULL (no field).  A nonzero field adds an ancilla spin
+ *       (index n) coupled to spin i by h_i and read as +1 (the whole configuration is
+ *       flipped otherwise), so the dynamics stays field-free and the reported energy is
+ *       -1/2 s^T J s - h^T s.
+ *   n : 1 <= n <= 16384.
+ * lambda_max and lambda_min of J are computed in binary64 on the host (Lanczos) when
+ * first needed: at gsb_init if c was not set, which then sets c = 1/lambda_max
+ * (App. A), or when read with gsb_get.  Needs no device memory yet.
+ * Errors: EINVAL, ENONFINITE, ENOTSYM, EDIAG, ENOMEM. */
+gsb_status gsb_create(const float* J, const float* h, int32_t n, gsb_ctx** out);
+
+/* Release all host and device resources (device memory bound with gsb_bind_workspace
+ * stays owned by the caller).  NULL is ignored. */
+void gsb_destroy(gsb_ctx* ctx);
+
+/* Set / read an option (gsb_option).  Errors: EINVAL (unknown option, read-only option,
+ * value out of range), EUNSUPPORTED (FP8 precision on J with entries outside {0,+-1}). */
+gsb_status gsb_set(gsb_ctx* ctx, int32_t option, double value);
+gsb_status gsb_get(gsb_ctx* ctx, int32_t option, double* value);
+
+/* Bind the HIP stream (hipStream_t) all device work of this context is enqueued on.
+ * NULL selects the null stream. */
+gsb_status gsb_set_stream(gsb_ctx* ctx, void* stream);
+
+/* Device memory a run of `replicas` replicas and `steps` time steps needs at the current
+ * precision, in bytes. */
+gsb_status gsb_workspace_size(gsb_ctx* ctx, int32_t replicas, int32_t steps, size_t* bytes);
+
+/* Bind caller-owned device memory (e.g. a framework allocation) as the workspace.
+ *   device_ptr : device, 256-byte aligned, `bytes` long; must outlive its use by the
+ *                context.  NULL unbinds (the library then allocates on demand).
+ * A bound workspace smaller than a later run needs makes that run fail with ENOMEM. */
+gsb_status gsb_bind_workspace(gsb_ctx* ctx, void* device_ptr, size_t bytes);
+
+/* Start a run: draw the initial state of `replicas` replicas from `seed` and set m = 0
+ * of an M = `steps` step schedule.  No time step is taken.
+ *   control_strength : A of eq. (7), 0 <= A; ignored (taken as 0) for bSB and dSB.
+ *   dt               : time step Delta_t > 0 (App. A: 1.25 for dense random J).
+ * Asynchronous on the context's stream.
+ * Errors: EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE. */
+gsb_status gsb_init(gsb_ctx* ctx, int32_t variant, int32_t schedule, double control_strength,
+                    double dt, int32_t replicas, int32_t steps, uint64_t seed);
+
+/* Advance the current run by `count` time steps (m -> m + count, m + count <= M).
+ * Asynchronous on the context's stream.  Errors: ESTATE, EINVAL, EDEVICE. */
+gsb_status gsb_step(gsb_ctx* ctx, int32_t count);
+
+/* gsb_init followed by all M steps and the final energies (Sec. III evaluates the cut
+ * only at the final time).  Asynchronous on the context's stream. */
+gsb_status gsb_run(gsb_ctx* ctx, int32_t variant, int32_t schedule, double control_strength,
+                   double dt, int32_t replicas, int32_t steps, uint64_t seed);
+
+/* Ising energies, eq. (1), of s = sgn(x) (sgn(0) = +1) at the current step, one per
+ * replica.  energies: host, `replicas` doubles.  Exact for integer J; binary64
+ * accumulation otherwise.  Synchronises the stream.  Errors: ESTATE, EINVAL, EDEVICE. */
+gsb_status gsb_energy(gsb_ctx* ctx, double* energies);
+
+/* The replica with the lowest energy (ties to the lowest index) and its spins.
+ *   spins   : host, n int8 values in {-1, +1}, or NULL.
+ *   energy  : host, or NULL.   replica : host, or NULL.
+ * Synchronises the stream.  Errors: ESTATE, EDEVICE. */
+gsb_status gsb_best(gsb_ctx* ctx, int8_t* spins, double* energy, int32_t* replica);
+
+/* All spins s = sgn(x) at the current step.  spins: host, replicas*n int8 (replica-major).
+ * Synchronises the stream. */
+gsb_status gsb_spins(gsb_ctx* ctx, int8_t* spins);
+
+/* Copy out the state at the current step.  x, y, p: host, replicas*n_dyn binary32 each
+ * (replica-major; n_dyn = GSB_OPT_N_DYN), any of them NULL to skip; m: host or NULL.
+ * Synchronises. */
+gsb_status gsb_state(gsb_ctx* ctx, float* x, float* y, float* p, int32_t* m);
+
+/* Replace the state of the current run (checkpoint resume): x, y, p host arrays as in
+ * gsb_state, all non-NULL and finite, |x| <= 1; 0 <= m <= M.  Synchronises.
+ * Errors: ESTATE, EINVAL, ENONFINITE, EDEVICE. */
+gsb_status gsb_set_state(gsb_ctx* ctx, const float* x, const float* y, const float* p, int32_t m);
+
+/* Device time of the last gsb_step/gsb_run time stepping (the persistent step kernel
+ * launches), in milliseconds, measured with HIP events on the context's stream.
+ * Synchronises the stream. */
+gsb_status gsb_last_step_ms(gsb_ctx* ctx, double* ms);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* gsb_last_error(void);
+
+/* Library version string. */
+const char* gsb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSB_H */

@@ -1,0 +1,680 @@
+// gsb_api.cpp -- the C ABI of libgsb (include/gsb.h): argument checking, instance
+// set-up, workspace management and the launch sequence of the gfx950 kernels.
+#include "../../include/gsb.h"
+#include "gsb_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace gsb;
+
+namespace {
+
+thread_local std::string g_err;
+
+gsb_status fail(gsb_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+gsb_status hip_fail(hipError_t e, const char* what) {
+  return fail(GSB_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                      \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int form_of(int precision) {
+  return precision == GSB_PREC_FP8 ? kFormFP8 : (precision == GSB_PREC_BF16X2 ? kFormBF16X2 : kFormFP32);
+}
+size_t operand_elem_bytes(int form) { return form == kFormFP8 ? 1 : (form == kFormBF16X2 ? 2 : 4); }
+
+// ---- eigenvalue bounds of a symmetric matrix (App. A needs lambda_max and lambda_min) ----
+// Lanczos with full reorthogonalisation, binary64; extreme Ritz values of the tridiagonal
+// matrix by Sturm-sequence bisection.
+int sturm_count(const std::vector<double>& a, const std::vector<double>& b, int k, double x) {
+  // number of eigenvalues of T_k smaller than x
+  int cnt = 0;
+  double d = 1.0;
+  for (int i = 0; i < k; ++i) {
+    const double bb = (i > 0) ? b[i - 1] * b[i - 1] : 0.0;
+    d = (a[i] - x) - (i > 0 ? bb / d : 0.0);
+    if (d == 0.0) d = -1e-300;
+    if (d < 0) ++cnt;
+  }
+  return cnt;
+}
+
+double tridiag_eig(const std::vector<double>& a, const std::vector<double>& b, int k, int idx) {
+  double lo = 0, hi = 0;
+  for (int i = 0; i < k; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (sturm_count(a, b, k, mid) > idx) hi = mid; else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+void extreme_eigenvalues(const std::vector<float>& J, int n, double* lmax, double* lmin) {
+  if (n == 1) { *lmax = 0.0; *lmin = 0.0; return; }
+  const int kmax = std::min(n, 400);
+  std::vector<std::vector<double>> V;
+  std::vector<double> alpha, beta;
+  std::vector<double> v(n), w(n);
+  uint64_t s = 0x243F6A8885A308D3ull;  // fixed start vector
+  double nrm = 0;
+  for (int i = 0; i < n; ++i) {
+    s += 0x9E3779B97F4A7C15ull;
+    uint64_t z = s;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    v[i] = (double)(z >> 11) * 0x1.0p-53 - 0.5;
+    nrm += v[i] * v[i];
+  }
+  nrm = std::sqrt(nrm);
+  for (auto& e : v) e /= nrm;
+  double prev_max = 0, prev_min = 0;
+  for (int k = 0; k < kmax; ++k) {
+    V.push_back(v);
+    for (int i = 0; i < n; ++i) {
+      double acc = 0;
+      const float* Ji = &J[(size_t)i * n];
+      for (int j = 0; j < n; ++j) acc += (double)Ji[j] * v[j];
+      w[i] = acc;
+    }
+    double a = 0;
+    for (int i = 0; i < n; ++i) a += w[i] * v[i];
+    alpha.push_back(a);
+    for (int pass = 0; pass < 2; ++pass)
+      for (const auto& u : V) {
+        double d = 0;
+        for (int i = 0; i < n; ++i) d += w[i] * u[i];
+        for (int i = 0; i < n; ++i) w[i] -= d * u[i];
+      }
+    double bnorm = 0;
+    for (int i = 0; i < n; ++i) bnorm += w[i] * w[i];
+    bnorm = std::sqrt(bnorm);
+    const int kk = k + 1;
+    if ((kk % 10 == 0) || kk == kmax || bnorm < 1e-12) {
+      const double emax = tridiag_eig(alpha, beta, kk, kk - 1);
+      const double emin = tridiag_eig(alpha, beta, kk, 0);
+      const double scale = std::max(std::fabs(emax), std::fabs(emin)) + 1e-300;
+      if (bnorm < 1e-12 || (kk >= 20 && std::fabs(emax - prev_max) < 1e-13 * scale &&
+                            std::fabs(emin - prev_min) < 1e-13 * scale) || kk == kmax) {
+        *lmax = emax;
+        *lmin = emin;
+        return;
+      }
+      prev_max = emax;
+      prev_min = emin;
+    }
+    beta.push_back(bnorm);
+    for (int i = 0; i < n; ++i) v[i] = w[i] / bnorm;
+  }
+  *lmax = prev_max;
+  *lmin = prev_min;
+}
+
+}  // namespace
+
+struct gsb_ctx {
+  // instance
+  int n_user = 0, n = 0, np = 0, anc = -1;
+  std::vector<float> J;  // n x n, row-major (with the ancilla row/column if any)
+  bool pm1 = false;
+  double c = 0;
+  bool c_set = false;
+  double lmax = 0, lmin = 0;
+  bool eig_done = false;
+  int precision = GSB_PREC_FP32;
+  int init_mode = GSB_INIT_X;
+  hipStream_t stream = nullptr;
+  // run
+  bool inited = false;
+  int variant = 0, schedule = 0, R = 0, rp = 0, M = 0, m = 0;
+  double A = 0, dt = 0;
+  uint64_t seed = 0;
+  int chunk_rp = 0;
+  bool jlds = false;
+  std::vector<float> rtab_host;
+  // device memory
+  void* ws_user = nullptr;
+  size_t ws_user_bytes = 0;
+  void* ws_own = nullptr;
+  size_t ws_own_bytes = 0;
+  uint8_t* ws = nullptr;   // current workspace base
+  size_t ws_bytes = 0;
+  // carved buffers (valid for the current workspace and shape)
+  float* j32 = nullptr;
+  uint8_t* jf = nullptr;
+  float* rtab = nullptr;
+  float *X = nullptr, *Y = nullptr, *P = nullptr;
+  uint8_t* Q = nullptr;
+  size_t q_buf_bytes = 0;
+  unsigned* sync = nullptr;
+  unsigned* status = nullptr;
+  double* partial = nullptr;
+  double* E = nullptr;
+  int* best_idx = nullptr;
+  double* best_e = nullptr;
+  int8_t* spins = nullptr;
+  // bookkeeping of what the workspace holds
+  bool j32_ready = false;
+  int jf_form = -1;
+  bool energy_valid = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool timed = false;
+};
+
+namespace {
+
+struct Layout {
+  size_t j32, jf, rtab, X, Y, P, Q, sync, status, partial, E, best, spins, total;
+  size_t q_buf_bytes;
+  int chunk_rp;
+};
+
+gsb_status plan(gsb_ctx* c, int R, int M, Layout* L, bool* jlds_out) {
+  const int form = form_of(c->precision);
+  const int np = c->np;
+  const int rp = (R + kBN - 1) / kBN * kBN;
+  const bool jlds = jlds_fits(form, np);
+  int dev_count = 0;
+  if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1)
+    return fail(GSB_EDEVICE, "no HIP device");
+  const int max_wg = max_coresident_workgroups(form, jlds, np);
+  if (max_wg < 1) return fail(GSB_EDEVICE, "occupancy query failed for the step kernel");
+  const int nb = np / kBM;
+  const int max_groups = max_wg / nb;
+  if (max_groups < 1)
+    return fail(GSB_EUNSUPPORTED, "n too large for one co-resident replica group on this device");
+  const int chunk_rp = std::min(rp, max_groups * kBN);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+  L->j32 = take((size_t)np * np * 4);
+  L->jf = take((size_t)np * np * operand_elem_bytes(form));
+  L->rtab = take((size_t)M * 4);
+  L->X = take((size_t)rp * np * 4);
+  L->Y = take((size_t)rp * np * 4);
+  L->P = take((size_t)rp * np * 4);
+  L->q_buf_bytes = (size_t)chunk_rp * np * operand_elem_bytes(form) * operand_planes(form);
+  L->Q = take(2 * L->q_buf_bytes);
+  L->sync = take(sync_words(chunk_rp / kBN) * 4);
+  L->status = take(256);
+  L->partial = take(energy_partial_doubles(np, rp) * 8);
+  L->E = take((size_t)rp * 8);
+  L->best = take(256);
+  L->spins = take((size_t)std::max(rp, 1) * c->n_user + 256);
+  L->total = off;
+  L->chunk_rp = chunk_rp;
+  *jlds_out = jlds;
+  return GSB_OK;
+}
+
+gsb_status ensure_workspace(gsb_ctx* c, size_t need) {
+  uint8_t* base = nullptr;
+  size_t bytes = 0;
+  if (c->ws_user) {
+    if (c->ws_user_bytes < need)
+      return fail(GSB_ENOMEM, "bound workspace has " + std::to_string(c->ws_user_bytes) + " bytes, run needs " +
+                                  std::to_string(need));
+    base = static_cast<uint8_t*>(c->ws_user);
+    bytes = c->ws_user_bytes;
+  } else {
+    if (c->ws_own_bytes < need) {
+      if (c->ws_own) {
+        hipStreamSynchronize(c->stream);
+        hipFree(c->ws_own);
+        c->ws_own = nullptr;
+        c->ws_own_bytes = 0;
+      }
+      void* p = nullptr;
+      if (hipMalloc(&p, need) != hipSuccess)
+        return fail(GSB_ENOMEM, "device allocation of " + std::to_string(need) + " bytes failed");
+      c->ws_own = p;
+      c->ws_own_bytes = need;
+    }
+    base = static_cast<uint8_t*>(c->ws_own);
+    bytes = c->ws_own_bytes;
+  }
+  if (base != c->ws || bytes != c->ws_bytes) {
+    c->ws = base;
+    c->ws_bytes = bytes;
+    c->j32_ready = false;
+    c->jf_form = -1;
+  }
+  return GSB_OK;
+}
+
+gsb_status ensure_eig(gsb_ctx* c) {
+  if (!c->eig_done) {
+    extreme_eigenvalues(c->J, c->n, &c->lmax, &c->lmin);
+    c->eig_done = true;
+  }
+  return GSB_OK;
+}
+
+gsb_status check_status_word(gsb_ctx* c) {
+  unsigned st = 0;
+  HIP_TRY(hipMemcpyAsync(&st, c->status, 4, hipMemcpyDeviceToHost, c->stream), "status read");
+  HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronise");
+  if (st != 0) return fail(GSB_EDEVICE, "step kernel: a replica-group barrier timed out");
+  return GSB_OK;
+}
+
+gsb_status compute_energy(gsb_ctx* c) {
+  if (c->energy_valid) return GSB_OK;
+  HIP_TRY(launch_energy(c->j32, c->n, c->np, c->rp, c->R, c->X, c->partial, c->E, c->stream), "energy kernel");
+  c->energy_valid = true;
+  return GSB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gsb_last_error(void) { return g_err.c_str(); }
+const char* gsb_version(void) { return "gsb-mi355x 0.1 (gfx950)"; }
+
+gsb_status gsb_create(const float* J, const float* h, int32_t n, gsb_ctx** out) {
+  g_err.clear();
+  if (!out) return fail(GSB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!J) return fail(GSB_EINVAL, "J is NULL");
+  if (n < 1 || n > 16384) return fail(GSB_EINVAL, "n must be in [1, 16384]");
+  for (size_t k = 0; k < (size_t)n * n; ++k)
+    if (!std::isfinite(J[k])) return fail(GSB_ENONFINITE, "J has a non-finite entry");
+  for (int i = 0; i < n; ++i) {
+    if (J[(size_t)i * n + i] != 0.0f) return fail(GSB_EDIAG, "J_ii != 0 at i = " + std::to_string(i));
+    for (int j = i + 1; j < n; ++j)
+      if (J[(size_t)i * n + j] != J[(size_t)j * n + i])
+        return fail(GSB_ENOTSYM, "J_ij != J_ji at (" + std::to_string(i) + ", " + std::to_string(j) + ")");
+  }
+  bool field = false;
+  if (h) {
+    for (int i = 0; i < n; ++i) {
+      if (!std::isfinite(h[i])) return fail(GSB_ENONFINITE, "h has a non-finite entry");
+      if (h[i] != 0.0f) field = true;
+    }
+  }
+  gsb_ctx* c = new (std::nothrow) gsb_ctx;
+  if (!c) return fail(GSB_ENOMEM, "host allocation failed");
+  c->n_user = n;
+  c->n = field ? n + 1 : n;
+  c->anc = field ? n : -1;
+  c->np = (c->n + kRowPad - 1) / kRowPad * kRowPad;
+  try {
+    c->J.assign((size_t)c->n * c->n, 0.0f);
+  } catch (...) {
+    delete c;
+    return fail(GSB_ENOMEM, "host allocation failed");
+  }
+  for (int i = 0; i < n; ++i) std::memcpy(&c->J[(size_t)i * c->n], &J[(size_t)i * n], sizeof(float) * n);
+  if (field)
+    for (int i = 0; i < n; ++i) {
+      c->J[(size_t)i * c->n + n] = h[i];
+      c->J[(size_t)n * c->n + i] = h[i];
+    }
+  c->pm1 = true;
+  for (float v : c->J)
+    if (!(v == 0.0f || v == 1.0f || v == -1.0f)) { c->pm1 = false; break; }
+  c->precision = c->pm1 ? GSB_PREC_FP8 : GSB_PREC_BF16X2;
+  *out = c;
+  return GSB_OK;
+}
+
+void gsb_destroy(gsb_ctx* c) {
+  if (!c) return;
+  if (c->ws_own) {
+    hipStreamSynchronize(c->stream);
+    hipFree(c->ws_own);
+  }
+  if (c->ev0) hipEventDestroy(c->ev0);
+  if (c->ev1) hipEventDestroy(c->ev1);
+  delete c;
+}
+
+gsb_status gsb_set(gsb_ctx* c, int32_t option, double v) {
+  g_err.clear();
+  if (!c) return fail(GSB_EINVAL, "ctx is NULL");
+  switch (option) {
+    case GSB_OPT_C:
+      if (!std::isfinite(v) || v <= 0) return fail(GSB_EINVAL, "c must be finite and > 0");
+      c->c = v;
+      c->c_set = true;
+      return GSB_OK;
+    case GSB_OPT_PRECISION: {
+      const int p = (int)v;
+      if ((double)p != v || p < GSB_PREC_FP32 || p > GSB_PREC_FP8) return fail(GSB_EINVAL, "unknown precision");
+      if (p == GSB_PREC_FP8 && !c->pm1)
+        return fail(GSB_EUNSUPPORTED, "FP8 precision needs J entries in {0, +1, -1}");
+      if (p != c->precision) {
+        c->precision = p;
+        c->inited = false;  // operand buffers change shape
+      }
+      return GSB_OK;
+    }
+    case GSB_OPT_INIT_MODE: {
+      const int mm = (int)v;
+      if ((double)mm != v || mm < GSB_INIT_X || mm > GSB_INIT_PM01) return fail(GSB_EINVAL, "unknown init mode");
+      c->init_mode = mm;
+      return GSB_OK;
+    }
+    default:
+      return fail(GSB_EINVAL, "unknown or read-only option " + std::to_string(option));
+  }
+}
+
+gsb_status gsb_get(gsb_ctx* c, int32_t option, double* v) {
+  g_err.clear();
+  if (!c || !v) return fail(GSB_EINVAL, "NULL argument");
+  switch (option) {
+    case GSB_OPT_C:
+      if (!c->c_set) {
+        ensure_eig(c);
+        *v = c->lmax > 0 ? 1.0 / c->lmax : 1.0;
+      } else {
+        *v = c->c;
+      }
+      return GSB_OK;
+    case GSB_OPT_PRECISION: *v = c->precision; return GSB_OK;
+    case GSB_OPT_INIT_MODE: *v = c->init_mode; return GSB_OK;
+    case GSB_OPT_LAMBDA_MAX: ensure_eig(c); *v = c->lmax; return GSB_OK;
+    case GSB_OPT_LAMBDA_MIN: ensure_eig(c); *v = c->lmin; return GSB_OK;
+    case GSB_OPT_N: *v = c->n_user; return GSB_OK;
+    case GSB_OPT_N_DYN: *v = c->n; return GSB_OK;
+    case GSB_OPT_STEP: *v = c->inited ? c->m : 0; return GSB_OK;
+    case GSB_OPT_REPLICAS: *v = c->inited ? c->R : 0; return GSB_OK;
+    case GSB_OPT_DT_STABLE:
+      ensure_eig(c);
+      // eq. (13): dt = D_t sqrt(2 / (1 - lambda_min / lambda_max)), D_t = 1.25
+      *v = (c->lmax > 0) ? 1.25 * std::sqrt(2.0 / (1.0 - c->lmin / c->lmax)) : 1.25;
+      return GSB_OK;
+    default:
+      return fail(GSB_EINVAL, "unknown option " + std::to_string(option));
+  }
+}
+
+gsb_status gsb_set_stream(gsb_ctx* c, void* stream) {
+  g_err.clear();
+  if (!c) return fail(GSB_EINVAL, "ctx is NULL");
+  c->stream = static_cast<hipStream_t>(stream);
+  return GSB_OK;
+}
+
+gsb_status gsb_workspace_size(gsb_ctx* c, int32_t replicas, int32_t steps, size_t* bytes) {
+  g_err.clear();
+  if (!c || !bytes) return fail(GSB_EINVAL, "NULL argument");
+  if (replicas < 1 || steps < 1) return fail(GSB_EINVAL, "replicas and steps must be >= 1");
+  Layout L;
+  bool jlds;
+  gsb_status s = plan(c, replicas, steps, &L, &jlds);
+  if (s != GSB_OK) return s;
+  *bytes = L.total;
+  return GSB_OK;
+}
+
+gsb_status gsb_bind_workspace(gsb_ctx* c, void* ptr, size_t bytes) {
+  g_err.clear();
+  if (!c) return fail(GSB_EINVAL, "ctx is NULL");
+  if (ptr && ((uintptr_t)ptr & 255)) return fail(GSB_EINVAL, "workspace must be 256-byte aligned");
+  c->ws_user = ptr;
+  c->ws_user_bytes = ptr ? bytes : 0;
+  c->inited = false;
+  c->ws = nullptr;
+  c->ws_bytes = 0;
+  c->j32_ready = false;
+  c->jf_form = -1;
+  return GSB_OK;
+}
+
+gsb_status gsb_init(gsb_ctx* c, int32_t variant, int32_t schedule, double A, double dt, int32_t replicas,
+                    int32_t steps, uint64_t seed) {
+  g_err.clear();
+  if (!c) return fail(GSB_EINVAL, "ctx is NULL");
+  if (variant < GSB_BSB || variant > GSB_GDSB) return fail(GSB_EINVAL, "unknown variant");
+  if (schedule < GSB_SCHED_LINEAR || schedule > GSB_SCHED_CONSTANT) return fail(GSB_EINVAL, "unknown schedule");
+  if (!std::isfinite(A) || A < 0) return fail(GSB_EINVAL, "control strength must be finite and >= 0");
+  if (!std::isfinite(dt) || dt <= 0) return fail(GSB_EINVAL, "dt must be finite and > 0");
+  if (replicas < 1 || replicas > (1 << 20)) return fail(GSB_EINVAL, "replicas must be in [1, 2^20]");
+  if (steps < 1 || steps > (1 << 24)) return fail(GSB_EINVAL, "steps must be in [1, 2^24]");
+  if (c->precision == GSB_PREC_FP8 && !c->pm1) return fail(GSB_EUNSUPPORTED, "FP8 precision needs J in {0, +-1}");
+  if (!c->c_set) {
+    ensure_eig(c);
+    c->c = c->lmax > 0 ? 1.0 / c->lmax : 1.0;  // App. A: c = 1 / lambda_max
+  }
+  Layout L;
+  bool jlds;
+  gsb_status s = plan(c, replicas, steps, &L, &jlds);
+  if (s != GSB_OK) return s;
+  s = ensure_workspace(c, L.total);
+  if (s != GSB_OK) return s;
+  const int form = form_of(c->precision);
+  const int rp = (replicas + kBN - 1) / kBN * kBN;
+  // carve
+  uint8_t* b = c->ws;
+  const bool j32_moved = reinterpret_cast<float*>(b + L.j32) != c->j32;
+  c->j32 = reinterpret_cast<float*>(b + L.j32);
+  if (reinterpret_cast<uint8_t*>(b + L.jf) != c->jf) c->jf_form = -1;
+  c->jf = b + L.jf;
+  if (j32_moved) { c->j32_ready = false; c->jf_form = -1; }
+  c->rtab = reinterpret_cast<float*>(b + L.rtab);
+  c->X = reinterpret_cast<float*>(b + L.X);
+  c->Y = reinterpret_cast<float*>(b + L.Y);
+  c->P = reinterpret_cast<float*>(b + L.P);
+  c->Q = b + L.Q;
+  c->q_buf_bytes = L.q_buf_bytes;
+  c->sync = reinterpret_cast<unsigned*>(b + L.sync);
+  c->status = reinterpret_cast<unsigned*>(b + L.status);
+  c->partial = reinterpret_cast<double*>(b + L.partial);
+  c->E = reinterpret_cast<double*>(b + L.E);
+  c->best_idx = reinterpret_cast<int*>(b + L.best);
+  c->best_e = reinterpret_cast<double*>(b + L.best + 8);
+  c->spins = reinterpret_cast<int8_t*>(b + L.spins);
+  c->chunk_rp = L.chunk_rp;
+  c->jlds = jlds;
+  // instance upload and encode
+  if (!c->j32_ready) {
+    HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(c->j32), (size_t)c->np * c->np, 0u, c->stream), "clear J");
+    HIP_TRY(hipMemcpy2DAsync(c->j32, (size_t)c->np * 4, c->J.data(), (size_t)c->n * 4, (size_t)c->n * 4, c->n,
+                             hipMemcpyHostToDevice, c->stream),
+            "upload J");
+    c->j32_ready = true;
+    c->jf_form = -1;
+  }
+  if (c->jf_form != form) {
+    HIP_TRY(launch_encode_j(form, c->j32, c->np, c->jf, c->stream), "encode J");
+    c->jf_form = form;
+  }
+  // schedule table r_m = 1 / (M - m) (eqs. (6), (7)), binary64 rounded once
+  c->rtab_host.assign(steps, 0.0f);
+  if (schedule == GSB_SCHED_LINEAR)
+    for (int m = 0; m < steps; ++m) c->rtab_host[m] = (float)(1.0 / (double)(steps - m));
+  HIP_TRY(hipMemcpyAsync(c->rtab, c->rtab_host.data(), (size_t)steps * 4, hipMemcpyHostToDevice, c->stream),
+          "upload schedule");
+  HIP_TRY(launch_fill_u32(c->status, 64, 0u, c->stream), "clear status");
+  HIP_TRY(launch_init_state(c->n, c->np, rp, seed, c->init_mode, c->X, c->Y, c->P, c->stream), "init state");
+  // make the pageable host sources safe to reuse
+  HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronise");
+  c->variant = variant;
+  c->schedule = schedule;
+  c->A = (variant == GSB_GBSB || variant == GSB_GDSB) ? A : 0.0;
+  c->dt = dt;
+  c->R = replicas;
+  c->rp = rp;
+  c->M = steps;
+  c->m = 0;
+  c->seed = seed;
+  c->inited = true;
+  c->energy_valid = false;
+  c->timed = false;
+  return GSB_OK;
+}
+
+gsb_status gsb_step(gsb_ctx* c, int32_t count) {
+  g_err.clear();
+  if (!c) return fail(GSB_EINVAL, "ctx is NULL");
+  if (!c->inited) return fail(GSB_ESTATE, "no run: call gsb_init or gsb_run first");
+  if (count < 0 || c->m + count > c->M) return fail(GSB_EINVAL, "step count beyond the schedule length M");
+  if (count == 0) return GSB_OK;
+  const int form = form_of(c->precision);
+  if (!c->ev0) {
+    HIP_TRY(hipEventCreate(&c->ev0), "event create");
+    HIP_TRY(hipEventCreate(&c->ev1), "event create");
+  }
+  HIP_TRY(hipEventRecord(c->ev0, c->stream), "event record");
+  for (int r0 = 0; r0 < c->rp; r0 += c->chunk_rp) {
+    const int rcount = std::min(c->chunk_rp, c->rp - r0);
+    StepArgs a;
+    a.n = c->n;
+    a.np = c->np;
+    a.rp = rcount;
+    a.groups = rcount / kBN;
+    a.nb = c->np / kBM;
+    a.discrete = (c->variant == GSB_DSB || c->variant == GSB_GDSB) ? 1 : 0;
+    a.m_begin = c->m;
+    a.m_end = c->m + count;
+    a.A = (float)c->A;
+    a.dt = (float)c->dt;
+    a.cdt = (float)(c->c * c->dt);
+    a.rtab = c->rtab;
+    a.jf = c->jf;
+    a.q = c->Q;
+    a.q_buf_bytes = (size_t)rcount * c->np * operand_elem_bytes(form) * operand_planes(form);
+    a.x = c->X + (size_t)r0 * c->np;
+    a.y = c->Y + (size_t)r0 * c->np;
+    a.p = c->P + (size_t)r0 * c->np;
+    a.sync = c->sync;
+    a.status = c->status;
+    HIP_TRY(launch_fill_u32(c->sync, sync_words(a.groups), 0u, c->stream), "clear sync");
+    HIP_TRY(launch_steps(form, c->jlds, a, c->stream), "step kernel launch");
+  }
+  HIP_TRY(hipEventRecord(c->ev1, c->stream), "event record");
+  c->timed = true;
+  c->m += count;
+  c->energy_valid = false;
+  return GSB_OK;
+}
+
+gsb_status gsb_run(gsb_ctx* c, int32_t variant, int32_t schedule, double A, double dt, int32_t replicas,
+                   int32_t steps, uint64_t seed) {
+  gsb_status s = gsb_init(c, variant, schedule, A, dt, replicas, steps, seed);
+  if (s != GSB_OK) return s;
+  s = gsb_step(c, steps);
+  if (s != GSB_OK) return s;
+  return compute_energy(c);
+}
+
+gsb_status gsb_energy(gsb_ctx* c, double* energies) {
+  g_err.clear();
+  if (!c || !energies) return fail(GSB_EINVAL, "NULL argument");
+  if (!c->inited) return fail(GSB_ESTATE, "no run");
+  gsb_status s = compute_energy(c);
+  if (s != GSB_OK) return s;
+  HIP_TRY(hipMemcpyAsync(energies, c->E, (size_t)c->R * 8, hipMemcpyDeviceToHost, c->stream), "copy energies");
+  return check_status_word(c);
+}
+
+gsb_status gsb_best(gsb_ctx* c, int8_t* spins, double* energy, int32_t* replica) {
+  g_err.clear();
+  if (!c) return fail(GSB_EINVAL, "ctx is NULL");
+  if (!c->inited) return fail(GSB_ESTATE, "no run");
+  gsb_status s = compute_energy(c);
+  if (s != GSB_OK) return s;
+  HIP_TRY(launch_best(c->E, c->R, c->best_idx, c->best_e, c->stream), "best kernel");
+  HIP_TRY(launch_spins(c->X, c->n_user, c->np, 0, 1, c->anc, c->best_idx, c->spins, c->stream), "spins kernel");
+  int bi = 0;
+  double be = 0;
+  HIP_TRY(hipMemcpyAsync(&bi, c->best_idx, 4, hipMemcpyDeviceToHost, c->stream), "copy best");
+  HIP_TRY(hipMemcpyAsync(&be, c->best_e, 8, hipMemcpyDeviceToHost, c->stream), "copy best");
+  if (spins)
+    HIP_TRY(hipMemcpyAsync(spins, c->spins, (size_t)c->n_user, hipMemcpyDeviceToHost, c->stream), "copy spins");
+  s = check_status_word(c);
+  if (s != GSB_OK) return s;
+  if (energy) *energy = be;
+  if (replica) *replica = bi;
+  return GSB_OK;
+}
+
+gsb_status gsb_spins(gsb_ctx* c, int8_t* spins) {
+  g_err.clear();
+  if (!c || !spins) return fail(GSB_EINVAL, "NULL argument");
+  if (!c->inited) return fail(GSB_ESTATE, "no run");
+  HIP_TRY(launch_spins(c->X, c->n_user, c->np, 0, c->R, c->anc, nullptr, c->spins, c->stream), "spins kernel");
+  HIP_TRY(hipMemcpyAsync(spins, c->spins, (size_t)c->R * c->n_user, hipMemcpyDeviceToHost, c->stream),
+          "copy spins");
+  return check_status_word(c);
+}
+
+gsb_status gsb_state(gsb_ctx* c, float* x, float* y, float* p, int32_t* m) {
+  g_err.clear();
+  if (!c) return fail(GSB_EINVAL, "ctx is NULL");
+  if (!c->inited) return fail(GSB_ESTATE, "no run");
+  float* src[3] = {c->X, c->Y, c->P};
+  float* dst[3] = {x, y, p};
+  for (int k = 0; k < 3; ++k)
+    if (dst[k])
+      HIP_TRY(hipMemcpy2DAsync(dst[k], (size_t)c->n * 4, src[k], (size_t)c->np * 4, (size_t)c->n * 4, c->R,
+                               hipMemcpyDeviceToHost, c->stream),
+              "copy state");
+  gsb_status s = check_status_word(c);
+  if (s != GSB_OK) return s;
+  if (m) *m = c->m;
+  return GSB_OK;
+}
+
+gsb_status gsb_set_state(gsb_ctx* c, const float* x, const float* y, const float* p, int32_t m) {
+  g_err.clear();
+  if (!c) return fail(GSB_EINVAL, "ctx is NULL");
+  if (!c->inited) return fail(GSB_ESTATE, "no run");
+  if (!x || !y || !p) return fail(GSB_EINVAL, "x, y and p are required");
+  if (m < 0 || m > c->M) return fail(GSB_EINVAL, "m outside [0, M]");
+  const size_t cnt = (size_t)c->R * c->n;
+  for (size_t k = 0; k < cnt; ++k) {
+    if (!std::isfinite(x[k]) || !std::isfinite(y[k]) || !std::isfinite(p[k]))
+      return fail(GSB_ENONFINITE, "state has a non-finite entry");
+    if (std::fabs(x[k]) > 1.0f) return fail(GSB_EINVAL, "|x| > 1 in the state (eq. (5) keeps |x| <= 1)");
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronise");
+  const float* src[3] = {x, y, p};
+  float* dst[3] = {c->X, c->Y, c->P};
+  for (int k = 0; k < 3; ++k)
+    HIP_TRY(hipMemcpy2DAsync(dst[k], (size_t)c->np * 4, src[k], (size_t)c->n * 4, (size_t)c->n * 4, c->R,
+                             hipMemcpyHostToDevice, c->stream),
+            "copy state");
+  HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronise");
+  c->m = m;
+  c->energy_valid = false;
+  return GSB_OK;
+}
+
+gsb_status gsb_last_step_ms(gsb_ctx* c, double* ms) {
+  g_err.clear();
+  if (!c || !ms) return fail(GSB_EINVAL, "NULL argument");
+  if (!c->timed) return fail(GSB_ESTATE, "no timed step yet");
+  HIP_TRY(hipEventSynchronize(c->ev1), "event synchronise");
+  float f = 0;
+  HIP_TRY(hipEventElapsedTime(&f, c->ev0, c->ev1), "event elapsed");
+  *ms = f;
+  return GSB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,63 @@
+// Internal interface between the C ABI (gsb_api.cpp) and the gfx950 kernels
+// (gsb_kernels.hip).  Not installed; not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace gsb {
+
+// Tile geometry of the persistent step kernel (one workgroup per tile, 4 waves).
+constexpr int kBM = 64;        // rows of J (spins i) per workgroup
+constexpr int kBN = 128;       // replica columns per workgroup (4 waves x 32)
+constexpr int kKS = 128;       // K (spins j) per k-step
+constexpr int kThreads = 256;
+constexpr int kRowPad = 128;   // np is a multiple of this (>= kBM, = kKS)
+
+enum Form { kFormFP32 = 0, kFormBF16X2 = 1, kFormFP8 = 2 };
+
+// Bytes of one operand plane per (16-replica block, k-step) and of one J block per
+// (16-row tile, k-step), in the fragment-major layouts.
+__host__ __device__ constexpr size_t operand_block_bytes(int form) {
+  return form == kFormFP8 ? 2048 : (form == kFormBF16X2 ? 4096 : 8192);
+}
+__host__ __device__ constexpr int operand_planes(int form) { return form == kFormBF16X2 ? 2 : 1; }
+
+struct StepArgs {
+  int n;          // spins carried by the dynamics (including an ancilla)
+  int np;         // padded spins (multiple of kRowPad)
+  int rp;         // replicas of this launch (multiple of kBN)
+  int groups;     // rp / kBN
+  int nb;         // np / kBM  (workgroups per replica group)
+  int discrete;   // 1: operand is sgn(x) (dSB, GdSB)
+  int m_begin, m_end;
+  float A, dt, cdt;
+  const float* rtab;      // r_m, m = 0..M-1
+  const void* jf;         // J in the fragment-major layout of `form`
+  uint8_t* q;             // operand ping-pong buffers of this launch
+  size_t q_buf_bytes;     // bytes of one ping-pong buffer (all planes)
+  float* x; float* y; float* p;  // state of this launch's replicas, [rp][np]
+  unsigned* sync;         // zeroed before the launch; see sync_words()
+  unsigned* status;       // set nonzero on a device-side timeout
+};
+
+inline size_t sync_words(int groups) { return (size_t)(3 * groups + 1) * 64; }
+
+// ---- launchers (all asynchronous on `stream`) ----
+hipError_t launch_fill_u32(unsigned* p, size_t count, unsigned v, hipStream_t stream);
+hipError_t launch_encode_j(int form, const float* j32, int np, void* jf, hipStream_t stream);
+hipError_t launch_init_state(int n, int np, int rp, uint64_t seed, int mode, float* x, float* y,
+                             float* p, hipStream_t stream);
+// Persistent step kernel.  `jlds` selects the LDS-resident J variant (FP8 only).
+hipError_t launch_steps(int form, bool jlds, const StepArgs& a, hipStream_t stream);
+int max_coresident_workgroups(int form, bool jlds, int np);
+bool jlds_fits(int form, int np);
+hipError_t launch_energy(const float* j32, int n, int np, int rp, int r_count, const float* x,
+                         double* partial, double* energies, hipStream_t stream);
+size_t energy_partial_doubles(int np, int rp);
+hipError_t launch_best(const double* energies, int r_count, int* best_idx, double* best_e,
+                       hipStream_t stream);
+hipError_t launch_spins(const float* x, int n_out, int np, int r_first, int r_count, int anc,
+                        const int* r_index, int8_t* spins, hipStream_t stream);
+
+}  // namespace gsb

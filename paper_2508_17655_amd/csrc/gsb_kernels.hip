@@ -1,0 +1,630 @@
+// gsb_kernels.hip -- gfx950 kernels of libgsb.
+//
+// Simulated bifurcation (Goto, Hidaka, Tatsumura, arXiv 2508.17655): every step is
+//   p_i <- p_i - [1 - A x_i^2] p_i / (M - m)                    eq. (7) (eq. (6) at A = 0)
+//   y_i <- y_i - p_i(t_{m+1}) x_i dt + c dt sum_j J_ij q_j      eq. (3), q = x or sgn(x)
+//   x_i <- x_i + y_i dt                                         eq. (4)
+//   |x_i| > 1  =>  x_i <- sgn(x_i), y_i <- 0                    eq. (5)
+// for R independent replicas at once (batch processing, Sec. VI).  The coupling product
+// of all replicas is one GEMM, G = J Q, with replicas as columns; it runs on MFMA and the
+// update above is fused into its epilogue, which also writes the next step's operand Q.
+//
+// Floating-point contraction is disabled for this file: the update is evaluated as one
+// binary32 operation per arithmetic operator, in the order written, so the sign and E4M3
+// forms reproduce a strict binary32 evaluation bit for bit.
+#include "gsb_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace gsb {
+namespace {
+
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int kPolicySc1 = 16;             // buffer-load cache policy: device scope (skips L1)
+constexpr unsigned kSpinLimit = 1u << 22;  // polls before a barrier gives up (seconds)
+constexpr int kHwRegXccId = 20 | (0 << 6) | ((4 - 1) << 11);  // hwreg(HW_REG_XCC_ID, 0, 4)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ v8i cat(v4i a, v4i b) {
+  return v8i{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+}
+
+__device__ __forceinline__ unsigned ld_dev(const unsigned* p) {
+  return __hip_atomic_load(const_cast<unsigned*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(unsigned* p, unsigned v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Barrier over the `nb` workgroups that share a replica group.  Every wave first waits
+// until its own stores are acknowledged (they are then in L2), then one thread counts
+// the workgroup in and polls the counter with device-scope loads.  When all members sit
+// on one XCD (`local`) they share that XCD's L2, and operand loads that skip L1 see the
+// data without any cache maintenance; otherwise the agent-scope release/acquire fences
+// write back and invalidate the caches between XCDs.
+__device__ __forceinline__ bool group_sync(unsigned* ctr, unsigned target, int local,
+                                           unsigned* abort_flag, unsigned* status, int* s_flag) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (!local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    unsigned spins = 0;
+    while (ld_dev(ctr) < target) {
+      ++spins;
+      if ((spins & 63u) == 0 && ld_dev(abort_flag)) { ok = 0; break; }
+      if (spins > kSpinLimit) { st_dev(abort_flag, 1u); st_dev(status, 1u); ok = 0; break; }
+    }
+    if (!local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *s_flag = ok;
+  }
+  __syncthreads();
+  return *s_flag != 0;
+}
+
+// ---------------------------------------------------------------------------------------
+// Operand encodings and their fragment-major placement.
+//
+// Q holds, per (16-replica block rb, 128-spin k-step kc), the operand bytes in exactly the
+// order the MFMA B operand is held in a wavefront's lanes, so a fragment is one coalesced
+// 1 KiB load per VGPR quad:
+//   FP8   : 2048 B = [half 2][lane 64][16 B];  lane = r%16 + 16*(kk/32),
+//           byte 16*half + b  <->  kk = 32*(lane/16) + 16*half + b            (16x16x128)
+//   BF16  : 4096 B per plane = [sub 4][lane 64][8 bf16]; kk = 32*sub + 8*(lane/16) + e
+//   FP32  : 8192 B = [grp 8][lane 64][4 f32];  kk = 16*grp + 4*(lane/16) + t, where
+//           element t feeds the t-th of four 16x16x4 MFMAs of that group.
+// (kk = k mod 128.)  J uses the same layouts with the row i in place of the replica r.
+// ---------------------------------------------------------------------------------------
+template <int FORM>
+__device__ __forceinline__ void store_operand(uint8_t* qbuf, size_t plane_bytes, int nks,
+                                              int ibase, int rcol, int lane, const float xv[4],
+                                              int discrete) {
+  const int rb = rcol >> 4;
+  const int kc = ibase >> 7;
+  const int kk0 = (ibase & 127) + 4 * (lane >> 4);  // first of this lane's 4 rows
+  if constexpr (FORM == kFormFP8) {
+    unsigned w;
+    if (discrete) {
+      w = 0x38383838u;  // +1.0 in E4M3 in every byte
+      w |= (xv[0] < 0.0f ? 0x80u : 0u) | (xv[1] < 0.0f ? 0x8000u : 0u) |
+           (xv[2] < 0.0f ? 0x800000u : 0u) | (xv[3] < 0.0f ? 0x80000000u : 0u);
+    } else {
+      int lo = __builtin_amdgcn_cvt_pk_fp8_f32(xv[0], xv[1], 0, false);
+      w = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(xv[2], xv[3], lo, true);
+    }
+    const int lanep = (lane & 15) + 16 * (kk0 >> 5);
+    const int half = (kk0 & 31) >> 4;
+    const size_t off = ((size_t)(rb * nks + kc) * 2 + half) * 1024 + lanep * 16 + (kk0 & 15);
+    *reinterpret_cast<unsigned*>(qbuf + off) = w;
+  } else if constexpr (FORM == kFormBF16X2) {
+    unsigned short hi[4], lo[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float q = discrete ? (xv[v] < 0.0f ? -1.0f : 1.0f) : xv[v];
+      __bf16 h = (__bf16)q;
+      float hf = (float)h;
+      __bf16 l = (__bf16)(q - hf);  // q - hf is exact in binary32
+      hi[v] = __builtin_bit_cast(unsigned short, h);
+      lo[v] = __builtin_bit_cast(unsigned short, l);
+    }
+    const int sub = kk0 >> 5;
+    const int lanep = (lane & 15) + 16 * ((kk0 & 31) >> 3);
+    const size_t off = ((size_t)(rb * nks + kc) * 4 + sub) * 1024 + lanep * 16 + (kk0 & 7) * 2;
+    v2u wh{(unsigned)hi[0] | ((unsigned)hi[1] << 16), (unsigned)hi[2] | ((unsigned)hi[3] << 16)};
+    v2u wl{(unsigned)lo[0] | ((unsigned)lo[1] << 16), (unsigned)lo[2] | ((unsigned)lo[3] << 16)};
+    *reinterpret_cast<v2u*>(qbuf + off) = wh;
+    *reinterpret_cast<v2u*>(qbuf + plane_bytes + off) = wl;
+  } else {
+    v4f q;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) q[v] = discrete ? (xv[v] < 0.0f ? -1.0f : 1.0f) : xv[v];
+    const int grp = kk0 >> 4;
+    const int lanep = (lane & 15) + 16 * ((kk0 & 15) >> 2);
+    const size_t off = ((size_t)(rb * nks + kc) * 8 + grp) * 1024 + lanep * 16;
+    *reinterpret_cast<v4f*>(qbuf + off) = q;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Persistent step kernel.  Workgroup (g, mb) owns spins [64 mb, 64 mb + 64) of replicas
+// [128 g, 128 g + 128); wave w owns replica columns [32 w, 32 w + 32) of that range, so
+// each wave computes a 64 x 32 tile of G = J Q (4 x 2 MFMA tiles of 16 x 16) and keeps
+// x, y, p of those 2048 elements in registers for the whole launch.  Workgroup b is
+// (g, mb) = (b mod groups, b div groups): with 8 or 16 groups, round-robin dispatch
+// puts each group on one XCD.
+// ---------------------------------------------------------------------------------------
+template <int FORM, bool JLDS>
+__global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  __shared__ int s_flag;
+  __shared__ int s_local;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = blockIdx.x % a.groups;
+  const int mb = blockIdx.x / a.groups;
+  const int row0 = mb * kBM;
+  const int col0 = g * kBN + wave * 32;
+  const int nks = a.np / kKS;
+  unsigned* ctr = a.sync + (size_t)g * 64;
+  unsigned* hs = a.sync + (size_t)(a.groups + g) * 64;
+  unsigned* msk = a.sync + (size_t)(2 * a.groups + g) * 64;
+  unsigned* abort_flag = a.sync + (size_t)(3 * a.groups) * 64;
+  const size_t jblk = operand_block_bytes(FORM);
+  const size_t plane_bytes = a.q_buf_bytes / operand_planes(FORM);
+
+  // J rows of this workgroup: 4 row tiles x nks k-steps, contiguous in the layout.
+  const uint8_t* jrows = static_cast<const uint8_t*>(a.jf) + (size_t)(row0 >> 4) * nks * jblk;
+  if constexpr (JLDS) {
+    const int total = 4 * nks * (int)(jblk / 16);
+    const v4u* src = reinterpret_cast<const v4u*>(jrows);
+    for (int t = tid; t < total; t += kThreads) reinterpret_cast<v4u*>(lds)[t] = src[t];
+  }
+
+  // State of this wave's 64 x 32 tile: lane holds rows 4*(lane/16)+v of column lane%16.
+  float xs[4][2][4], ys[4][2][4], ps[4][2][4];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const int i = row0 + rt * 16 + 4 * (lane >> 4);
+      const int r = col0 + ct * 16 + (lane & 15);
+      const size_t o = (size_t)r * a.np + i;
+      v4f vx = *reinterpret_cast<const v4f*>(a.x + o);
+      v4f vy = *reinterpret_cast<const v4f*>(a.y + o);
+      v4f vp = *reinterpret_cast<const v4f*>(a.p + o);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) { xs[rt][ct][v] = vx[v]; ys[rt][ct][v] = vy[v]; ps[rt][ct][v] = vp[v]; }
+    }
+
+  // Handshake: learn whether all members of this group run on one XCD.
+  if (tid == 0) {
+    const unsigned xcc = (unsigned)__builtin_amdgcn_s_getreg(kHwRegXccId) & 15u;
+    __hip_atomic_fetch_or(msk, 1u << xcc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(hs, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    unsigned spins = 0;
+    while (ld_dev(hs) < (unsigned)a.nb) {
+      ++spins;
+      if ((spins & 63u) == 0 && ld_dev(abort_flag)) { ok = 0; break; }
+      if (spins > kSpinLimit) { st_dev(abort_flag, 1u); st_dev(a.status, 1u); ok = 0; break; }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    s_local = (__builtin_popcount(ld_dev(msk)) == 1) ? 1 : 0;
+    s_flag = ok;
+  }
+  __syncthreads();
+  bool alive = s_flag != 0;
+  const int local = s_local;
+
+  // Operand of the starting state, then the first group barrier.
+  if (alive) {
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+        store_operand<FORM>(a.q, plane_bytes, nks, row0 + rt * 16, col0 + ct * 16, lane,
+                            xs[rt][ct], a.discrete);
+    alive = group_sync(ctr, (unsigned)a.nb, local, abort_flag, a.status, &s_flag);
+  }
+
+  const float A = a.A, dt = a.dt, cdt = a.cdt;
+  const int steps = a.m_end - a.m_begin;
+  for (int s = 0; alive && s < steps; ++s) {
+    const int m = a.m_begin + s;
+    const uint8_t* qcur = a.q + (size_t)(s & 1) * a.q_buf_bytes;
+    uint8_t* qnext = a.q + (size_t)((s + 1) & 1) * a.q_buf_bytes;
+    const __amdgpu_buffer_rsrc_t qr = make_rsrc(qcur, a.q_buf_bytes);
+    const int rb0 = col0 >> 4;
+
+    v4f acc[4][2];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+
+    if constexpr (FORM == kFormFP8) {
+      for (int ks = 0; ks < nks; ++ks) {
+        v8i bq[2];
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          const unsigned base = (unsigned)(((rb0 + ct) * nks + ks) * 2048 + lane * 16);
+          v4i lo = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kPolicySc1));
+          v4i hi = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base + 1024, 0, kPolicySc1));
+          bq[ct] = cat(lo, hi);
+        }
+        v8i aj[4];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+          const size_t o = (size_t)(rt * nks + ks) * 2048 + lane * 16;
+          const uint8_t* pa = JLDS ? (lds + o) : (jrows + o);
+          aj[rt] = cat(*reinterpret_cast<const v4i*>(pa), *reinterpret_cast<const v4i*>(pa + 1024));
+        }
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct)
+            acc[rt][ct] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(aj[rt], bq[ct], acc[rt][ct],
+                                                                           0, 0, 0, 127, 0, 127);
+      }
+    } else if constexpr (FORM == kFormBF16X2) {
+      const int planes = a.discrete ? 1 : 2;  // sgn(x) has no low part
+      for (int ks = 0; ks < nks; ++ks) {
+#pragma unroll
+        for (int sub = 0; sub < 4; ++sub) {
+          v8bf aj[4];
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt) {
+            const size_t o = ((size_t)(rt * nks + ks) * 4 + sub) * 1024 + lane * 16;
+            aj[rt] = *reinterpret_cast<const v8bf*>(jrows + o);
+          }
+          for (int pl = 0; pl < planes; ++pl) {
+            v8bf bq[2];
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) {
+              const unsigned base = (unsigned)(pl * plane_bytes + ((size_t)((rb0 + ct) * nks + ks) * 4 + sub) * 1024 + lane * 16);
+              bq[ct] = __builtin_bit_cast(v8bf, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kPolicySc1));
+            }
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+              for (int ct = 0; ct < 2; ++ct)
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aj[rt], bq[ct], acc[rt][ct], 0, 0, 0);
+          }
+        }
+      }
+    } else {  // FP32
+      for (int ks = 0; ks < nks; ++ks) {
+        for (int grp = 0; grp < 8; ++grp) {
+          v4f aj[4], bq[2];
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt) {
+            const size_t o = ((size_t)(rt * nks + ks) * 8 + grp) * 1024 + lane * 16;
+            aj[rt] = *reinterpret_cast<const v4f*>(jrows + o);
+          }
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) {
+            const unsigned base = (unsigned)(((size_t)((rb0 + ct) * nks + ks) * 8 + grp) * 1024 + lane * 16);
+            bq[ct] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kPolicySc1));
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+              for (int ct = 0; ct < 2; ++ct)
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(aj[rt][t], bq[ct][t], acc[rt][ct], 0, 0, 0);
+        }
+      }
+    }
+
+    // Fused update, eqs. (7), (3), (4), (5), in binary32, one rounding per operator.
+    const float rm = a.rtab[m];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float x = xs[rt][ct][v], y = ys[rt][ct][v], p = ps[rt][ct][v];
+          const float gsum = acc[rt][ct][v];
+          const float xx = x * x;
+          const float ax = A * xx;
+          const float f = 1.0f - ax;
+          const float fp = f * p;
+          const float dp = fp * rm;
+          const float pn = p - dp;        // p_i(t_{m+1}), eq. (7)
+          const float px = pn * x;
+          const float pxdt = px * dt;
+          const float y1 = y - pxdt;      // y + dy
+          const float gy = cdt * gsum;    // Dy = c dt sum_j J_ij q_j
+          float yn = y1 + gy;             // eq. (3)
+          const float dx = yn * dt;
+          float xn = x + dx;              // eq. (4)
+          if (__builtin_fabsf(xn) > 1.0f) {  // eq. (5)
+            xn = xn > 0.0f ? 1.0f : -1.0f;
+            yn = 0.0f;
+          }
+          xs[rt][ct][v] = xn; ys[rt][ct][v] = yn; ps[rt][ct][v] = pn;
+        }
+        store_operand<FORM>(qnext, plane_bytes, nks, row0 + rt * 16, col0 + ct * 16, lane,
+                            xs[rt][ct], a.discrete);
+      }
+    alive = group_sync(ctr, (unsigned)((s + 2) * a.nb), local, abort_flag, a.status, &s_flag);
+  }
+
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const int i = row0 + rt * 16 + 4 * (lane >> 4);
+      const int r = col0 + ct * 16 + (lane & 15);
+      const size_t o = (size_t)r * a.np + i;
+      *reinterpret_cast<v4f*>(a.x + o) = v4f{xs[rt][ct][0], xs[rt][ct][1], xs[rt][ct][2], xs[rt][ct][3]};
+      *reinterpret_cast<v4f*>(a.y + o) = v4f{ys[rt][ct][0], ys[rt][ct][1], ys[rt][ct][2], ys[rt][ct][3]};
+      *reinterpret_cast<v4f*>(a.p + o) = v4f{ps[rt][ct][0], ps[rt][ct][1], ps[rt][ct][2], ps[rt][ct][3]};
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Small kernels.
+// ---------------------------------------------------------------------------------------
+__global__ void k_fill_u32(unsigned* p, size_t count, unsigned v) {
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (size_t)gridDim.x * blockDim.x)
+    p[t] = v;
+}
+
+// J (row-major np x np binary32, zero padded) -> fragment-major layout of `FORM`.
+template <int FORM>
+__global__ void k_encode_j(const float* j32, int np, uint8_t* jf) {
+  const size_t total = (size_t)np * np;
+  const int nks = np / kKS;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t / np), k = (int)(t % np);
+    const float v = j32[t];
+    const int rt = i >> 4, kc = k >> 7, kk = k & 127;
+    if constexpr (FORM == kFormFP8) {
+      const int lanep = (i & 15) + 16 * (kk >> 5);
+      const size_t off = ((size_t)(rt * nks + kc) * 2 + ((kk & 31) >> 4)) * 1024 + lanep * 16 + (kk & 15);
+      jf[off] = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xFF);
+    } else if constexpr (FORM == kFormBF16X2) {
+      const int lanep = (i & 15) + 16 * ((kk & 31) >> 3);
+      const size_t off = ((size_t)(rt * nks + kc) * 4 + (kk >> 5)) * 1024 + lanep * 16 + (kk & 7) * 2;
+      *reinterpret_cast<__bf16*>(jf + off) = (__bf16)v;
+    } else {
+      const int lanep = (i & 15) + 16 * ((kk & 15) >> 2);
+      const size_t off = ((size_t)(rt * nks + kc) * 8 + (kk >> 4)) * 1024 + lanep * 16 + (kk & 3) * 4;
+      *reinterpret_cast<float*>(jf + off) = v;
+    }
+  }
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): output k (k >= 1) of the generator seeded with s
+// is mix(s + k * 0x9E3779B97F4A7C15).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ float uniform_pm01(uint64_t z) {
+  const double u = (double)(z >> 11) * 0x1.0p-53;  // [0, 1)
+  const double t = 0.2 * u;
+  return (float)(-0.1 + t);                          // U(-0.1, 0.1), App. A
+}
+
+// Initial state: counter (2 r + stream) n + i, draw number counter + 1.
+__global__ void k_init_state(int n, int np, int rp, uint64_t seed, int mode, float* x, float* y, float* p) {
+  const size_t total = (size_t)rp * np;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)(t / np), i = (int)(t % np);
+    float xv = 0.0f, yv = 0.0f;
+    if (i < n) {
+      const uint64_t c0 = (uint64_t)(2 * (int64_t)r) * (uint64_t)n + (uint64_t)i;
+      const uint64_t z0 = splitmix64(seed, c0 + 1);
+      if (mode == 2) {
+        xv = (z0 >> 63) ? -0.1f : 0.1f;  // the chaos start of Sec. IV
+      } else {
+        xv = uniform_pm01(z0);
+        if (mode == 1) yv = uniform_pm01(splitmix64(seed, c0 + (uint64_t)n + 1));
+      }
+    }
+    x[t] = xv;
+    y[t] = yv;
+    p[t] = 1.0f;  // p_i(0) = 1
+  }
+}
+
+// Energy, eq. (1): E_r = -1/2 sum_i s_i h_i with h_i = sum_j J_ij s_j, s = sgn(x).
+// Block (bx, by): replicas 16 bx .. 16 bx + 15, rows i = 256 by + threadIdx.x.  J is read
+// as J_ji (= J_ij) so a wavefront's loads are contiguous.  Partial sums per row block
+// are reduced in a fixed order (deterministic, exact for integer J).
+constexpr int kERep = 16;
+constexpr int kEChunk = 2048;
+__global__ void __launch_bounds__(256) k_energy_partial(const float* j32, int n, int np, int rp,
+                                                        const float* x, double* partial) {
+  __shared__ int8_t s[kERep][kEChunk];
+  __shared__ double red[4][kERep];
+  const int i = blockIdx.y * 256 + threadIdx.x;
+  const int r0 = blockIdx.x * kERep;
+  double h[kERep];
+#pragma unroll
+  for (int rr = 0; rr < kERep; ++rr) h[rr] = 0.0;
+  for (int j0 = 0; j0 < n; j0 += kEChunk) {
+    const int jn = min(kEChunk, n - j0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < kERep * kEChunk; t += 256) {
+      const int rr = t / kEChunk, jj = t % kEChunk;
+      s[rr][jj] = (jj < jn) ? (x[(size_t)(r0 + rr) * np + j0 + jj] >= 0.0f ? 1 : -1) : 0;
+    }
+    __syncthreads();
+    if (i < n) {
+      for (int jj = 0; jj < jn; ++jj) {
+        const double jv = (double)j32[(size_t)(j0 + jj) * np + i];
+#pragma unroll
+        for (int rr = 0; rr < kERep; ++rr) h[rr] += jv * (double)s[rr][jj];
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int rr = 0; rr < kERep; ++rr) {
+    double v = 0.0;
+    if (i < n) v = (x[(size_t)(r0 + rr) * np + i] >= 0.0f) ? h[rr] : -h[rr];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wave][rr] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kERep) {
+    const int rr = threadIdx.x;
+    partial[(size_t)blockIdx.y * rp + r0 + rr] = ((red[0][rr] + red[1][rr]) + red[2][rr]) + red[3][rr];
+  }
+}
+
+__global__ void k_energy_final(const double* partial, int nyb, int rp, int r_count, double* E) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= r_count) return;
+  double acc = 0.0;
+  for (int b = 0; b < nyb; ++b) acc += partial[(size_t)b * rp + r];
+  E[r] = -0.5 * acc;
+}
+
+// argmin_r E_r, ties to the lowest r.
+__global__ void __launch_bounds__(256) k_best(const double* E, int r_count, int* best_idx, double* best_e) {
+  __shared__ double se[256];
+  __shared__ int si[256];
+  double be = __builtin_inf();
+  int bi = 0x7FFFFFFF;
+  for (int r = threadIdx.x; r < r_count; r += 256) {
+    const double e = E[r];
+    if (e < be || (e == be && r < bi)) { be = e; bi = r; }
+  }
+  se[threadIdx.x] = be;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const double e2 = se[threadIdx.x + w];
+      const int i2 = si[threadIdx.x + w];
+      if (e2 < se[threadIdx.x] || (e2 == se[threadIdx.x] && i2 < si[threadIdx.x])) {
+        se[threadIdx.x] = e2;
+        si[threadIdx.x] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { *best_idx = si[0]; *best_e = se[0]; }
+}
+
+// s = sgn(x) for replicas r_first .. r_first + r_count - 1 (or the single replica
+// *r_index when given).  With an ancilla spin `anc` (>= 0) the configuration is flipped
+// so that the ancilla reads +1.
+__global__ void k_spins(const float* x, int n_out, int np, int r_first, int r_count, int anc,
+                        const int* r_index, int8_t* spins) {
+  const size_t total = (size_t)r_count * n_out;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(t / n_out), i = (int)(t % n_out);
+    const int r = r_index ? *r_index : r_first + k;
+    const float* xr = x + (size_t)r * np;
+    const bool flip = anc >= 0 && xr[anc] < 0.0f;
+    const bool up = xr[i] >= 0.0f;
+    spins[t] = (up != flip) ? 1 : -1;
+  }
+}
+
+inline int grid_for(size_t total, int block) {
+  size_t g = (total + block - 1) / block;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+template <int FORM, bool JLDS>
+const void* steps_kernel() {
+  return reinterpret_cast<const void*>(&k_steps<FORM, JLDS>);
+}
+
+const void* steps_kernel_for(int form, bool jlds) {
+  switch (form) {
+    case kFormFP8: return jlds ? steps_kernel<kFormFP8, true>() : steps_kernel<kFormFP8, false>();
+    case kFormBF16X2: return steps_kernel<kFormBF16X2, false>();
+    default: return steps_kernel<kFormFP32, false>();
+  }
+}
+
+size_t steps_lds_bytes(int form, bool jlds, int np) {
+  return jlds ? (size_t)4 * (np / kKS) * operand_block_bytes(form) : 0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------------------
+hipError_t launch_fill_u32(unsigned* p, size_t count, unsigned v, hipStream_t stream) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(count, 256)), dim3(256), 0, stream, p, count, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_j(int form, const float* j32, int np, void* jf, hipStream_t stream) {
+  const size_t total = (size_t)np * np;
+  const dim3 grid(grid_for(total, 256)), block(256);
+  uint8_t* out = static_cast<uint8_t*>(jf);
+  if (form == kFormFP8) hipLaunchKernelGGL(k_encode_j<kFormFP8>, grid, block, 0, stream, j32, np, out);
+  else if (form == kFormBF16X2) hipLaunchKernelGGL(k_encode_j<kFormBF16X2>, grid, block, 0, stream, j32, np, out);
+  else hipLaunchKernelGGL(k_encode_j<kFormFP32>, grid, block, 0, stream, j32, np, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_state(int n, int np, int rp, uint64_t seed, int mode, float* x, float* y,
+                             float* p, hipStream_t stream) {
+  hipLaunchKernelGGL(k_init_state, dim3(grid_for((size_t)rp * np, 256)), dim3(256), 0, stream, n, np,
+                     rp, seed, mode, x, y, p);
+  return hipGetLastError();
+}
+
+bool jlds_fits(int form, int np) {
+  return form == kFormFP8 && steps_lds_bytes(form, true, np) <= 160 * 1024 - 64;
+}
+
+int max_coresident_workgroups(int form, bool jlds, int np) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const void* k = steps_kernel_for(form, jlds);
+  const size_t lds = steps_lds_bytes(form, jlds, np);
+  if (lds > 0) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kThreads, lds) != hipSuccess) return 0;
+  return per_cu * cus;
+}
+
+hipError_t launch_steps(int form, bool jlds, const StepArgs& a, hipStream_t stream) {
+  const void* k = steps_kernel_for(form, jlds);
+  const size_t lds = steps_lds_bytes(form, jlds, a.np);
+  if (lds > 0) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  StepArgs copy = a;
+  void* args[] = {&copy};
+  return hipLaunchCooperativeKernel(k, dim3(a.groups * a.nb), dim3(kThreads), args, (unsigned)lds, stream);
+}
+
+size_t energy_partial_doubles(int np, int rp) { return (size_t)(np / 256 + 1) * rp; }
+
+hipError_t launch_energy(const float* j32, int n, int np, int rp, int r_count, const float* x,
+                         double* partial, double* energies, hipStream_t stream) {
+  const int nyb = (n + 255) / 256;
+  hipLaunchKernelGGL(k_energy_partial, dim3(rp / kERep, nyb), dim3(256), 0, stream, j32, n, np, rp, x, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_energy_final, dim3((r_count + 255) / 256), dim3(256), 0, stream, partial, nyb, rp,
+                     r_count, energies);
+  return hipGetLastError();
+}
+
+hipError_t launch_best(const double* energies, int r_count, int* best_idx, double* best_e, hipStream_t stream) {
+  hipLaunchKernelGGL(k_best, dim3(1), dim3(256), 0, stream, energies, r_count, best_idx, best_e);
+  return hipGetLastError();
+}
+
+hipError_t launch_spins(const float* x, int n_out, int np, int r_first, int r_count, int anc,
+                        const int* r_index, int8_t* spins, hipStream_t stream) {
+  hipLaunchKernelGGL(k_spins, dim3(grid_for((size_t)r_count * n_out, 256)), dim3(256), 0, stream, x, n_out,
+                     np, r_first, r_count, anc, r_index, spins);
+  return hipGetLastError();
+}
+
+}  // namespace gsb

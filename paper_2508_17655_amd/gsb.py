@@ -1,0 +1,288 @@
+"""ctypes binding of libgsb (include/gsb.h) -- argument marshalling only.
+
+Every function carries the name of the C entry point it calls.  All computation of the
+method happens in the library's gfx950 kernels; this module never falls back to host
+arithmetic and raises when the library is missing.
+
+``GSB`` is a convenience wrapper that gives the library a PyTorch-owned device workspace
+and PyTorch's current HIP stream (PyTorch is used for device memory and streams only).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgsb.so")
+
+# enums of gsb.h
+GSB_OK, GSB_EINVAL, GSB_ENOTSYM, GSB_EDIAG, GSB_ENONFINITE = 0, -1, -2, -3, -4
+GSB_ENOMEM, GSB_EDEVICE, GSB_ESTATE, GSB_EUNSUPPORTED = -5, -6, -7, -8
+GSB_BSB, GSB_DSB, GSB_GBSB, GSB_GDSB = 0, 1, 2, 3
+GSB_SCHED_LINEAR, GSB_SCHED_CONSTANT = 0, 1
+GSB_PREC_FP32, GSB_PREC_BF16X2, GSB_PREC_FP8 = 0, 1, 2
+GSB_INIT_X, GSB_INIT_XY, GSB_INIT_PM01 = 0, 1, 2
+(GSB_OPT_C, GSB_OPT_PRECISION, GSB_OPT_INIT_MODE, GSB_OPT_LAMBDA_MAX, GSB_OPT_LAMBDA_MIN, GSB_OPT_N,
+ GSB_OPT_STEP, GSB_OPT_REPLICAS, GSB_OPT_DT_STABLE, GSB_OPT_N_DYN) = range(10)
+
+VARIANTS = {"bsb": GSB_BSB, "dsb": GSB_DSB, "gbsb": GSB_GBSB, "gsb": GSB_GBSB, "gdsb": GSB_GDSB}
+PRECISIONS = {"fp32": GSB_PREC_FP32, "bf16x2": GSB_PREC_BF16X2, "fp8": GSB_PREC_FP8}
+
+STATUS_NAMES = {0: "GSB_OK", -1: "GSB_EINVAL", -2: "GSB_ENOTSYM", -3: "GSB_EDIAG", -4: "GSB_ENONFINITE",
+                -5: "GSB_ENOMEM", -6: "GSB_EDEVICE", -7: "GSB_ESTATE", -8: "GSB_EUNSUPPORTED"}
+
+# Every symbol include/gsb.h declares.
+SYMBOLS = ("gsb_create", "gsb_destroy", "gsb_set", "gsb_get", "gsb_set_stream", "gsb_workspace_size",
+           "gsb_bind_workspace", "gsb_init", "gsb_step", "gsb_run", "gsb_energy", "gsb_best", "gsb_spins",
+           "gsb_state", "gsb_set_state", "gsb_last_step_ms", "gsb_last_error", "gsb_version")
+
+
+class GsbError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgsb.so and declare the signatures of every entry point."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libgsb.so is not built ({path}); run `python -m paper_2508_17655_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, u64, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "gsb_create": (i32, [vp, vp, i32, ctypes.POINTER(vp)]),
+        "gsb_destroy": (None, [vp]),
+        "gsb_set": (i32, [vp, i32, dbl]),
+        "gsb_get": (i32, [vp, i32, ctypes.POINTER(dbl)]),
+        "gsb_set_stream": (i32, [vp, vp]),
+        "gsb_workspace_size": (i32, [vp, i32, i32, ctypes.POINTER(sz)]),
+        "gsb_bind_workspace": (i32, [vp, vp, sz]),
+        "gsb_init": (i32, [vp, i32, i32, dbl, dbl, i32, i32, u64]),
+        "gsb_step": (i32, [vp, i32]),
+        "gsb_run": (i32, [vp, i32, i32, dbl, dbl, i32, i32, u64]),
+        "gsb_energy": (i32, [vp, vp]),
+        "gsb_best": (i32, [vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(i32)]),
+        "gsb_spins": (i32, [vp, vp]),
+        "gsb_state": (i32, [vp, vp, vp, vp, ctypes.POINTER(i32)]),
+        "gsb_set_state": (i32, [vp, vp, vp, vp, i32]),
+        "gsb_last_step_ms": (i32, [vp, ctypes.POINTER(dbl)]),
+        "gsb_last_error": (ctypes.c_char_p, []),
+        "gsb_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != GSB_OK:
+        raise GsbError(status, where, gsb_last_error())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def gsb_last_error() -> str:
+    return load_library().gsb_last_error().decode()
+
+
+def gsb_version() -> str:
+    return load_library().gsb_version().decode()
+
+
+def gsb_create(J: np.ndarray, h: np.ndarray | None = None):
+    J = np.ascontiguousarray(J, dtype=np.float32)
+    if J.ndim != 2 or J.shape[0] != J.shape[1]:
+        raise ValueError("J must be a square matrix")
+    hh = None if h is None else np.ascontiguousarray(h, dtype=np.float32)
+    out = ctypes.c_void_p()
+    _check(load_library().gsb_create(_ptr(J), None if hh is None else _ptr(hh), J.shape[0], ctypes.byref(out)),
+           "gsb_create")
+    return out
+
+
+def gsb_destroy(ctx) -> None:
+    load_library().gsb_destroy(ctx)
+
+
+def gsb_set(ctx, option: int, value: float) -> None:
+    _check(load_library().gsb_set(ctx, option, float(value)), "gsb_set")
+
+
+def gsb_get(ctx, option: int) -> float:
+    v = ctypes.c_double()
+    _check(load_library().gsb_get(ctx, option, ctypes.byref(v)), "gsb_get")
+    return v.value
+
+
+def gsb_set_stream(ctx, stream: int | None) -> None:
+    _check(load_library().gsb_set_stream(ctx, ctypes.c_void_p(stream or 0)), "gsb_set_stream")
+
+
+def gsb_workspace_size(ctx, replicas: int, steps: int) -> int:
+    v = ctypes.c_size_t()
+    _check(load_library().gsb_workspace_size(ctx, replicas, steps, ctypes.byref(v)), "gsb_workspace_size")
+    return v.value
+
+
+def gsb_bind_workspace(ctx, device_ptr: int | None, nbytes: int) -> None:
+    _check(load_library().gsb_bind_workspace(ctx, ctypes.c_void_p(device_ptr or 0), nbytes), "gsb_bind_workspace")
+
+
+def gsb_init(ctx, variant: int, schedule: int, control_strength: float, dt: float, replicas: int, steps: int,
+             seed: int) -> None:
+    _check(load_library().gsb_init(ctx, variant, schedule, control_strength, dt, replicas, steps,
+                                   seed & (2**64 - 1)), "gsb_init")
+
+
+def gsb_step(ctx, count: int) -> None:
+    _check(load_library().gsb_step(ctx, count), "gsb_step")
+
+
+def gsb_run(ctx, variant: int, schedule: int, control_strength: float, dt: float, replicas: int, steps: int,
+            seed: int) -> None:
+    _check(load_library().gsb_run(ctx, variant, schedule, control_strength, dt, replicas, steps,
+                                  seed & (2**64 - 1)), "gsb_run")
+
+
+def gsb_energy(ctx) -> np.ndarray:
+    R = int(gsb_get(ctx, GSB_OPT_REPLICAS))
+    E = np.empty(R, dtype=np.float64)
+    _check(load_library().gsb_energy(ctx, _ptr(E)), "gsb_energy")
+    return E
+
+
+def gsb_best(ctx):
+    n = int(gsb_get(ctx, GSB_OPT_N))
+    s = np.empty(n, dtype=np.int8)
+    e = ctypes.c_double()
+    r = ctypes.c_int32()
+    _check(load_library().gsb_best(ctx, _ptr(s), ctypes.byref(e), ctypes.byref(r)), "gsb_best")
+    return s, e.value, r.value
+
+
+def gsb_spins(ctx) -> np.ndarray:
+    R = int(gsb_get(ctx, GSB_OPT_REPLICAS))
+    n = int(gsb_get(ctx, GSB_OPT_N))
+    s = np.empty((R, n), dtype=np.int8)
+    _check(load_library().gsb_spins(ctx, _ptr(s)), "gsb_spins")
+    return s
+
+
+def gsb_state(ctx):
+    R = int(gsb_get(ctx, GSB_OPT_REPLICAS))
+    n = int(gsb_get(ctx, GSB_OPT_N_DYN))
+    x = np.empty((R, n), dtype=np.float32)
+    y = np.empty((R, n), dtype=np.float32)
+    p = np.empty((R, n), dtype=np.float32)
+    m = ctypes.c_int32()
+    _check(load_library().gsb_state(ctx, _ptr(x), _ptr(y), _ptr(p), ctypes.byref(m)), "gsb_state")
+    return x, y, p, m.value
+
+
+def gsb_set_state(ctx, x: np.ndarray, y: np.ndarray, p: np.ndarray, m: int) -> None:
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    p = np.ascontiguousarray(p, dtype=np.float32)
+    _check(load_library().gsb_set_state(ctx, _ptr(x), _ptr(y), _ptr(p), m), "gsb_set_state")
+
+
+def gsb_last_step_ms(ctx) -> float:
+    v = ctypes.c_double()
+    _check(load_library().gsb_last_step_ms(ctx, ctypes.byref(v)), "gsb_last_step_ms")
+    return v.value
+
+
+class GSB:
+    """One Ising instance on the current HIP device, with a PyTorch-owned workspace.
+
+    >>> g = GSB(J, precision="fp8", c=1 / (2 * np.sqrt(n)))
+    >>> g.run("gbsb", A=0.2, dt=1.25, replicas=1024, steps=2000, seed=1)
+    >>> spins, energy, replica = g.best()
+    """
+
+    def __init__(self, J: np.ndarray, h: np.ndarray | None = None, *, precision: str | None = None,
+                 c: float | None = None, init_mode: int | None = None):
+        import torch  # device memory and streams only
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("GSB needs a HIP device")
+        self._torch = torch
+        self.ctx = gsb_create(J, h)
+        self._ws = None
+        if precision is not None:
+            gsb_set(self.ctx, GSB_OPT_PRECISION, PRECISIONS[precision])
+        if c is not None:
+            gsb_set(self.ctx, GSB_OPT_C, c)
+        if init_mode is not None:
+            gsb_set(self.ctx, GSB_OPT_INIT_MODE, init_mode)
+
+    def close(self):
+        if self.ctx is not None:
+            gsb_destroy(self.ctx)
+            self.ctx = None
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _prepare(self, replicas: int, steps: int):
+        torch = self._torch
+        need = gsb_workspace_size(self.ctx, replicas, steps)
+        if self._ws is None or self._ws.numel() < need + 256:
+            self._ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+            base = self._ws.data_ptr()
+            aligned = (base + 255) // 256 * 256
+            gsb_bind_workspace(self.ctx, aligned, need + 256 - (aligned - base))
+        gsb_set_stream(self.ctx, torch.cuda.current_stream().cuda_stream)
+
+    def init(self, variant, *, A: float = 0.0, dt: float, replicas: int, steps: int, seed: int,
+             schedule: int = GSB_SCHED_LINEAR):
+        v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        self._prepare(replicas, steps)
+        gsb_init(self.ctx, v, schedule, A, dt, replicas, steps, seed)
+
+    def step(self, count: int):
+        gsb_set_stream(self.ctx, self._torch.cuda.current_stream().cuda_stream)
+        gsb_step(self.ctx, count)
+
+    def run(self, variant, *, A: float = 0.0, dt: float, replicas: int, steps: int, seed: int,
+            schedule: int = GSB_SCHED_LINEAR):
+        v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        self._prepare(replicas, steps)
+        gsb_run(self.ctx, v, schedule, A, dt, replicas, steps, seed)
+
+    def energy(self) -> np.ndarray:
+        return gsb_energy(self.ctx)
+
+    def best(self):
+        return gsb_best(self.ctx)
+
+    def spins(self) -> np.ndarray:
+        return gsb_spins(self.ctx)
+
+    def state(self):
+        return gsb_state(self.ctx)
+
+    def set_state(self, x, y, p, m):
+        gsb_set_state(self.ctx, x, y, p, m)
+
+    def last_step_ms(self) -> float:
+        return gsb_last_step_ms(self.ctx)
+
+    def get(self, option: int) -> float:
+        return gsb_get(self.ctx, option)

@@ -1,0 +1,235 @@
+"""GPU path (libgsb through its C ABI) against the CPU oracle, element by element.
+
+Bars (derived in the design notes):
+  - sign products (dSB, GdSB) in every precision and the E4M3 product of bSB/GbSB in the
+    FP8 form: bit-exact x, y, p, spins and energies against the oracle's strict binary32
+    mode, because every partial sum of those products is exactly representable;
+  - continuous products in the FP32 and BF16X2 forms: one step from an identical state
+    within 1e-5 (relative, L2 over a replica) of the binary64 step; over 100 steps no
+    further from the binary64 trajectory than the strict binary32 oracle is, times 4,
+    floored at 1e-5.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2508_17655_amd import gsb, instances
+
+pytestmark = pytest.mark.gpu
+
+FORM_OF = {"fp8": 1, "fp32": 0, "bf16x2": 2}  # oracle operand form of a continuous product
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make(J, precision, c, init_mode=gsb.GSB_INIT_X):
+    return gsb.GSB(J, precision=precision, c=c, init_mode=init_mode)
+
+
+def oracle_start(orc, n, R, seed, init_mode):
+    x, y = orc.init_state(n, R, seed, init_mode)
+    return x, y, np.ones_like(x)
+
+
+def check_exact(a, b, what):
+    if not np.array_equal(a, b):
+        bad = np.argwhere(a != b)
+        raise AssertionError(f"{what}: {len(bad)} elements differ, first at {bad[0].tolist()}: "
+                             f"{a[tuple(bad[0])]!r} vs {b[tuple(bad[0])]!r}")
+
+
+@pytest.mark.parametrize("variant", ["dsb", "gdsb", "gbsb", "bsb"])
+def test_small_exact_forms_bitexact(orc, variant):
+    # N = 200, 16 replicas, 1000 steps, dt = 0.5, x and y ~ U(-0.1, 0.1): the small workload.
+    n, R, M, dt, A, seed = 200, 16, 1000, 0.5, 0.2, 11
+    say(f"case small-exact variant={variant} n={n} R={R} M={M}")
+    J = instances.dense_pm1(n, 1)
+    c = instances.paper_c(n)
+    g = make(J, "fp8", c, gsb.GSB_INIT_XY)
+    g.run(variant, A=A, dt=dt, replicas=R, steps=M, seed=seed)
+    x, y, p, m = g.state()
+    E = g.energy()
+    s_best, e_best, r_best = g.best()
+    spins = g.spins()
+    g.close()
+    assert m == M
+    x0, y0, p0 = oracle_start(orc, n, R, seed, orc.INIT_XY)
+    v = orc.VARIANTS[variant]
+    form = orc.FORM_E4M3 if variant in ("bsb", "gbsb") else orc.FORM_EXACT
+    xo, yo, po = orc.run(J, v, A=A, dt=dt, c=c, steps=M, x=x0, y=y0, p=p0, form=form, mode="fp32")
+    check_exact(x, xo, "x"); check_exact(y, yo, "y"); check_exact(p, po, "p")
+    so = orc.spins(xo)
+    check_exact(spins, so, "spins")
+    Eo = orc.energy(J, so)
+    check_exact(E, Eo, "energies")
+    assert r_best == orc.best(Eo) and e_best == Eo.min()
+    check_exact(s_best, so[r_best], "best spins")
+
+
+@pytest.mark.parametrize("precision", ["fp8", "bf16x2", "fp32"])
+@pytest.mark.parametrize("variant", ["dsb", "gdsb"])
+def test_ragged_sign_products_bitexact(orc, precision, variant):
+    # n not a multiple of the 128-spin k-step and R not a multiple of the 128-replica
+    # group: padding rows and padded replicas must not leak into the result.
+    n, R, M, seed = 333, 200, 300, 5
+    say(f"case ragged-sign precision={precision} variant={variant} n={n} R={R}")
+    J = instances.dense_pm1(n, 2)
+    c = instances.paper_c(n)
+    g = make(J, precision, c)
+    g.run(variant, A=0.3, dt=1.25, replicas=R, steps=M, seed=seed)
+    x, y, p, _ = g.state()
+    E = g.energy()
+    g.close()
+    x0, y0, p0 = oracle_start(orc, n, R, seed, orc.INIT_X)
+    xo, yo, po = orc.run(J, orc.VARIANTS[variant], A=0.3, dt=1.25, c=c, steps=M, x=x0, y=y0, p=p0, mode="fp32")
+    check_exact(x, xo, "x"); check_exact(y, yo, "y"); check_exact(p, po, "p")
+    check_exact(E, orc.energy(J, orc.spins(xo)), "energies")
+
+
+def test_chained_launches_equal_one_launch(orc):
+    # M steps in one persistent launch == the same steps in several launches (the state,
+    # operand and barrier hand-over between launches is exact) == oracle.
+    n, R, M, seed = 256, 256, 240, 3
+    say(f"case chained n={n} R={R} M={M}")
+    J = instances.dense_pm1(n, 4)
+    c = instances.paper_c(n)
+    g = make(J, "fp8", c)
+    g.init("gdsb", A=0.25, dt=1.25, replicas=R, steps=M, seed=seed)
+    g.step(M)
+    a = g.state()
+    g.init("gdsb", A=0.25, dt=1.25, replicas=R, steps=M, seed=seed)
+    for k in (1, 7, 32, 100, 100):
+        g.step(k)
+    b = g.state()
+    # resume from a checkpoint taken at step 120
+    g.init("gdsb", A=0.25, dt=1.25, replicas=R, steps=M, seed=seed)
+    g.step(120)
+    ck = g.state()
+    g.init("gdsb", A=0.25, dt=1.25, replicas=R, steps=M, seed=seed + 1)
+    g.set_state(ck[0], ck[1], ck[2], ck[3])
+    g.step(M - 120)
+    c2 = g.state()
+    g.close()
+    for u, v, w in zip(a[:3], b[:3], c2[:3]):
+        check_exact(u, v, "chained")
+        check_exact(u, w, "resumed")
+    x0, y0, p0 = oracle_start(orc, n, R, seed, orc.INIT_X)
+    xo = orc.run(J, orc.GDSB, A=0.25, dt=1.25, c=c, steps=M, x=x0, y=y0, p=p0, mode="fp32")[0]
+    check_exact(a[0], xo, "x vs oracle")
+
+
+def test_determinism(orc):
+    n, R, M = 500, 384, 200
+    say(f"case determinism n={n} R={R}")
+    J = instances.dense_pm1(n, 6)
+    g = make(J, "fp8", instances.paper_c(n))
+    out = []
+    for _ in range(2):
+        g.run("gbsb", A=0.2, dt=1.25, replicas=R, steps=M, seed=77)
+        out.append(g.state()[:3])
+    g.close()
+    for u, v in zip(*out):
+        assert u.tobytes() == v.tobytes()
+
+
+@pytest.mark.parametrize("variant", ["gdsb", "gbsb"])
+def test_full_size_sampled_bitexact(orc, variant):
+    # The benchmark launch: N = 2000 dense +-1, 1024 replicas, 2000 steps, dt = 1.25,
+    # FP8 product.  Replicas are independent, so a sample of them is checked against the
+    # oracle over the whole run, and all of them for the energy/spin consistency.
+    n, R, M, A, seed = 2000, 1024, 2000, 0.2, 2024
+    say(f"case full-size variant={variant} n={n} R={R} M={M}")
+    J = instances.dense_pm1(n, 2)
+    c = instances.paper_c(n)
+    g = make(J, "fp8", c)
+    g.run(variant, A=A, dt=1.25, replicas=R, steps=M, seed=seed)
+    x, y, p, _ = g.state()
+    E = g.energy()
+    spins = g.spins()
+    g.close()
+    sample = np.array([0, 1, 517, 1023])
+    x0, y0, p0 = oracle_start(orc, n, R, seed, orc.INIT_X)
+    form = orc.FORM_E4M3 if variant == "gbsb" else orc.FORM_EXACT
+    xo, yo, po = orc.run(J, orc.VARIANTS[variant], A=A, dt=1.25, c=c, steps=M, x=x0[sample], y=y0[sample],
+                         p=p0[sample], form=form, mode="fp32")
+    check_exact(x[sample], xo, "x"); check_exact(y[sample], yo, "y"); check_exact(p[sample], po, "p")
+    # every replica: energies are those of its spins
+    check_exact(spins, orc.spins(x), "spins")
+    check_exact(E, orc.energy(J, spins), "energies")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x2"])
+def test_continuous_forms_error_bounds(orc, precision):
+    # bSB with a continuous product: one step from an identical state, and 100 steps.
+    n, R, M, seed = 2000, 128, 2000, 9
+    say(f"case continuous precision={precision} n={n} R={R}")
+    J = instances.dense_pm1(n, 2)
+    c = instances.paper_c(n)
+    g = make(J, precision, c)
+    g.init("bsb", dt=1.25, replicas=R, steps=M, seed=seed)
+    samp = np.arange(4)
+    x0, y0, p0 = oracle_start(orc, n, R, seed, orc.INIT_X)
+    kw = dict(dt=1.25, c=c, steps=M)
+    # 40 steps in binary64 to get a state off the initial one, then one step on both sides
+    xs, ys, ps = orc.run(J, orc.BSB, x=x0, y=y0, p=p0, m_end=40, mode="fp64", **kw)
+    g.set_state(xs.astype(np.float32), ys.astype(np.float32), ps.astype(np.float32), 40)
+    g.step(1)
+    xg = g.state()[0][samp]
+    x64 = orc.run(J, orc.BSB, x=xs[samp].astype(np.float32), y=ys[samp].astype(np.float32),
+                  p=ps[samp].astype(np.float32), m_begin=40, m_end=41, mode="fp64", **kw)[0]
+    rel1 = np.linalg.norm(xg - x64, axis=1) / np.linalg.norm(x64, axis=1)
+    say(f"  one-step relative error {rel1.max():.3e}")
+    assert rel1.max() <= 1e-5
+    # trajectory over the first 100 steps
+    g.init("bsb", dt=1.25, replicas=R, steps=M, seed=seed)
+    traj = []
+    for _ in range(100):
+        g.step(1)
+        traj.append(g.state()[0][samp])
+    g.close()
+    traj = np.stack(traj, axis=1)
+    t64 = orc.run(J, orc.BSB, x=x0[samp], y=y0[samp], p=p0[samp], m_end=100, mode="fp64", record=True, **kw)[3]
+    t32 = orc.run(J, orc.BSB, x=x0[samp], y=y0[samp], p=p0[samp], m_end=100, mode="fp32", record=True, **kw)[3]
+    e_gpu = np.linalg.norm(traj - t64, axis=2) / np.linalg.norm(t64, axis=2)
+    e_f32 = np.linalg.norm(t32 - t64, axis=2) / np.linalg.norm(t64, axis=2)
+    say(f"  100-step error gpu {e_gpu.max():.3e} strict-fp32 {e_f32.max():.3e}; "
+        f"first step where strict fp32 exceeds 1e-5: {int(np.argmax(e_f32.max(0) > 1e-5))}")
+    assert np.all(e_gpu <= np.maximum(1e-5, 4 * e_f32))
+
+
+def test_real_weighted_energy_fp64(orc):
+    # J_ij ~ N(0,1)/sqrt(N) (not exact in FP8): BF16X2 product; the final energy is binary64.
+    n, R, M, seed = 300, 128, 200, 4
+    say(f"case real-weighted n={n}")
+    J = instances.dense_gaussian(n, 3)
+    g = gsb.GSB(J)  # default: BF16X2, c = 1/lambda_max (App. A)
+    lmax = g.get(gsb.GSB_OPT_LAMBDA_MAX)
+    assert abs(lmax - np.linalg.eigvalsh(J.astype(np.float64))[-1]) < 1e-8
+    dt = g.get(gsb.GSB_OPT_DT_STABLE)
+    g.run("gbsb", A=0.2, dt=dt, replicas=R, steps=M, seed=seed)
+    spins = g.spins()
+    E = g.energy()
+    g.close()
+    Eo = orc.energy(J, spins)
+    np.testing.assert_allclose(E, Eo, rtol=1e-13, atol=1e-12)
+
+
+def test_field_ancilla_energy(orc):
+    n, R, M = 40, 128, 300
+    say(f"case field n={n}")
+    J = instances.dense_pm1(n, 8)
+    h = np.where(np.arange(n) % 3 == 0, 1.0, -1.0).astype(np.float32)
+    g = gsb.GSB(J, h, c=instances.paper_c(n + 1), precision="fp8")
+    g.run("gdsb", A=0.2, dt=1.25, replicas=R, steps=M, seed=1)
+    s = g.spins()
+    E = g.energy()
+    sb, eb, rb = g.best()
+    g.close()
+    # E = -1/2 s^T J s - h^T s for the returned (gauge-fixed) spins
+    ref = orc.energy(J, s) - s.astype(np.float64) @ h.astype(np.float64)
+    check_exact(E, ref, "energy with field")
+    assert eb == ref.min() and rb == int(np.argmin(ref))
