@@ -1,0 +1,220 @@
+"""Benchmark: replica-spin-steps/s and TTS99 of GSB at N = 2000, dense +-1, on one MI355X.
+
+One bench step = one whole pass of the hot path on a batch: gsb_run (initial state of
+1024 replicas, 2000 symplectic-Euler steps with the fused eq. (7)/(3)/(4)/(5) update, and
+the eq. (1) energies) followed by gsb_best (argmin and its spins).  The instance is a
+synthetic stand-in for K2000 (Sec. III): J_ij iid uniform on {-1, +1}, generated from a
+seed, already resident in HBM when timing starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep] [--no-cpu]
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N, R, M, DT, A_HEAD, SEED_J = 2000, 1024, 2000, 1.25, 0.2, 2
+A_SWEEP = [0.05, 0.10, 0.15, 0.20, 0.25, 0.30, 0.35, 0.40]
+FP8_PEAK = 5.0e15      # MI355X dense FP8 MFMA, FLOP/s
+FP32_MFMA_PEAK = 157.3e12
+
+
+def tts99(t_com: float, p_run: float) -> float:
+    """TTS = T_com ln(1 - 0.99)/ln(1 - P_S), or T_com when P_S > 0.99 (Sec. VI)."""
+    if p_run > 0.99:
+        return t_com
+    if p_run <= 0.0:
+        return math.inf
+    return t_com * math.log(0.01) / math.log(1.0 - p_run)
+
+
+def _finite(v: float):
+    return v if math.isfinite(v) else None
+
+
+def kernel_source_hash() -> str:
+    with open(os.path.join(ROOT, "paper_2508_17655_amd", "csrc", "gsb_kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(name: str):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(J, c, target_s: float = 12.0):
+    """The oracle as it stands (strict binary32 update, E4M3 product, the FP8 form's
+    arithmetic) on a bounded sample of the same run: all host threads, one replica each."""
+    import numpy as np
+
+    import oracle
+
+    threads = oracle.num_threads()
+    x0, y0 = oracle.init_state(N, threads, 7)
+    t0 = time.perf_counter()
+    oracle.run(J, oracle.GBSB, A=A_HEAD, dt=DT, c=c, steps=M, x=x0, y=y0, m_end=2, form=oracle.FORM_E4M3,
+               mode="fp32")
+    per_step = (time.perf_counter() - t0) / 2  # one step of `threads` replicas
+    want = max(4, int(target_s / max(per_step, 1e-6)))
+    reps, steps = (threads, want) if want <= M else (threads * math.ceil(want / M), M)
+    x0, y0 = oracle.init_state(N, reps, 7)
+    t0 = time.perf_counter()
+    oracle.run(J, oracle.GBSB, A=A_HEAD, dt=DT, c=c, steps=M, x=x0, y=y0, m_end=steps, form=oracle.FORM_E4M3,
+               mode="fp32")
+    el = time.perf_counter() - t0
+    return {"value": reps * N * steps / el, "unit": "replica-spin-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} replicas x {steps} of the {M} steps (GbSB, A={A_HEAD}, E4M3 product, strict "
+                      f"binary32 update) of the N={N} instance, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-sweep", action="store_true", help="skip the P_S/TTS99 sweep")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--profile", action="store_true", help="few untimed runs only (for rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (replicas would shard "
+              "with one final argmin all-reduce; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2508_17655_amd import gsb, instances
+
+    torch.cuda.set_device(0)
+    J = instances.dense_pm1(N, SEED_J)
+    c = instances.paper_c(N)
+    g8 = gsb.GSB(J, precision="fp8", c=c)
+
+    if args.profile:
+        for s in range(3):
+            g8.run("gbsb", A=A_HEAD, dt=DT, replicas=R, steps=M, seed=100 + s)
+            g8.best()
+        # a plain copy of known size, for scaling the HBM byte counters
+        a = torch.empty(256 * 2**20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_runs": 3, "copy_bytes": a.numel()}))
+        return
+
+    # ---- timed region: the headline form (GbSB, FP8 E4M3 product) ----
+    for s in range(args.warmup):
+        g8.run("gbsb", A=A_HEAD, dt=DT, replicas=R, steps=M, seed=1000 + s)
+        g8.best()
+    torch.cuda.synchronize()
+    kernel_ms = []
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        g8.run("gbsb", A=A_HEAD, dt=DT, replicas=R, steps=M, seed=2000 + s)
+        g8.best()
+        kernel_ms.append(g8.last_step_ms())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1000 * elapsed / args.steps
+    rss = R * N * M / (elapsed / args.steps)
+    k_ms = float(np.mean(kernel_ms))
+    flop = 2.0 * N * N * R * M  # algorithmic J.Q FLOP of one launch
+    achieved = flop / (k_ms * 1e-3) / 1e12
+
+    # ---- the FP32 form of the same run (comparison, not the headline) ----
+    g32 = gsb.GSB(J, precision="fp32", c=c)
+    g32.run("gbsb", A=A_HEAD, dt=DT, replicas=R, steps=M, seed=999)
+    g32.best()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nrep32 = 2
+    k32 = []
+    for s in range(nrep32):
+        g32.run("gbsb", A=A_HEAD, dt=DT, replicas=R, steps=M, seed=3000 + s)
+        g32.best()
+        k32.append(g32.last_step_ms())
+    torch.cuda.synchronize()
+    ms32 = 1000 * (time.perf_counter() - t1) / nrep32
+    fp32_form = {"value": R * N * M / (ms32 * 1e-3), "unit": "replica-spin-steps/s", "ms_per_run": ms32,
+                 "kernel_ms": float(np.mean(k32)),
+                 "mfma_frac": flop / (float(np.mean(k32)) * 1e-3) / FP32_MFMA_PEAK}
+
+    out = {
+        "metric": "replica-spin-steps/s (GSB = GbSB, FP8 E4M3 product) at N=2000 dense +-1; TTS99; FP8 vs FP32 form",
+        "value": rss,
+        "unit": "replica-spin-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp8",
+        "data": "synthetic",
+        "config": {"workload": f"dense +-1 Ising N={N} (K2000 stand-in), GbSB A={A_HEAD}, {R} replicas x {M} steps, "
+                               f"dt={DT}, c=1/(2 sqrt N), FP8 E4M3 product, binary32 update",
+                   "n": N, "replicas": R, "steps_per_run": M, "dt": DT, "A": A_HEAD, "instance_seed": SEED_J},
+        "fp32_form": fp32_form,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP8_PEAK / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved * 1e12 / FP8_PEAK, "traffic": load_traffic("k_steps_fp8_n2000_r1024_counters.json"),
+                     "kernel": "k_steps<FP8, J in LDS>", "kernel_ms_per_launch": k_ms,
+                     "flop_per_launch": flop},
+    }
+
+    # ---- success probability and TTS99 (Sec. VI definitions), FP8 vs FP32 form ----
+    if not args.no_sweep:
+        runs = []
+        t_com = {"fp8": ms_per_step * 1e-3, "fp32": ms32 * 1e-3}
+        for form, g in (("fp8", g8), ("fp32", g32)):
+            for variant, A in [("bsb", 0.0)] + [("gbsb", a) for a in A_SWEEP]:
+                g.run(variant, A=A, dt=DT, replicas=R, steps=M, seed=5000)
+                runs.append((form, variant, A, g.energy()))
+        for variant, A in [("dsb", 0.0)] + [("gdsb", a) for a in A_SWEEP]:
+            g8.run(variant, A=A, dt=DT, replicas=R, steps=M, seed=5000)
+            runs.append(("fp8", variant, A, g8.energy()))
+        e_star = min(float(E.min()) for *_, E in runs)
+        table = []
+        for form, variant, A, E in runs:
+            p = float(np.mean(E == e_star))
+            p_run = 1.0 - (1.0 - p) ** R
+            table.append({"form": form, "variant": variant, "A": A, "p_hat": p,
+                          "dp_hat": math.sqrt(max(p - p * p, 0.0) / R), "best": float(E.min()),
+                          "mean": float(E.mean()),
+                          "tts99_s": _finite(tts99(t_com[form], p_run))})
+        best_row = {f: max((t for t in table if t["form"] == f and t["variant"] == "gbsb"), key=lambda t: t["p_hat"])
+                    for f in ("fp8", "fp32")}
+        out["success"] = {"e_star": e_star, "cut_star": -0.5 * (float(np.triu(J, 1).sum()) + e_star),
+                          "tts_semantics": "T_com = one launch of all replicas; P_S of the batch = 1-(1-p_hat)^R",
+                          "best_gbsb": best_row, "table": table}
+        out["tts99_s"] = best_row["fp8"]["tts99_s"]
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(J.astype(np.float64), c)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
