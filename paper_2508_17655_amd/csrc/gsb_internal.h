@@ -12,7 +12,8 @@ constexpr int kBM = 64;        // rows of J (spins i) per workgroup
 constexpr int kBN = 128;       // replica columns per workgroup (4 waves x 32)
 constexpr int kKS = 128;       // K (spins j) per k-step
 constexpr int kThreads = 256;
-constexpr int kRowPad = 128;   // np is a multiple of this (>= kBM, = kKS)
+constexpr int kKStepsUnroll = 4;  // k-steps per software-pipeline round
+constexpr int kRowPad = kKS * kKStepsUnroll;  // np is a multiple of this (512)
 
 enum Form { kFormFP32 = 0, kFormBF16X2 = 1, kFormFP8 = 2 };
 

@@ -14,6 +14,8 @@
 // forms reproduce a strict binary32 evaluation bit for bit.
 #include "gsb_internal.h"
 
+#include <algorithm>
+
 #pragma clang fp contract(off)
 
 namespace gsb {
@@ -86,16 +88,16 @@ __device__ __forceinline__ bool group_sync(unsigned* ctr, unsigned target, int l
 //           element t feeds the t-th of four 16x16x4 MFMAs of that group.
 // (kk = k mod 128.)  J uses the same layouts with the row i in place of the replica r.
 // ---------------------------------------------------------------------------------------
-template <int FORM>
+template <int FORM, bool DISC>
 __device__ __forceinline__ void store_operand(uint8_t* qbuf, size_t plane_bytes, int nks,
-                                              int ibase, int rcol, int lane, const float xv[4],
-                                              int discrete) {
+                                              int ibase, int rcol, int lane, const float xv[4]) {
+  constexpr bool discrete = DISC;
   const int rb = rcol >> 4;
   const int kc = ibase >> 7;
   const int kk0 = (ibase & 127) + 4 * (lane >> 4);  // first of this lane's 4 rows
   if constexpr (FORM == kFormFP8) {
     unsigned w;
-    if (discrete) {
+    if constexpr (discrete) {
       w = 0x38383838u;  // +1.0 in E4M3 in every byte
       w |= (xv[0] < 0.0f ? 0x80u : 0u) | (xv[1] < 0.0f ? 0x8000u : 0u) |
            (xv[2] < 0.0f ? 0x800000u : 0u) | (xv[3] < 0.0f ? 0x80000000u : 0u);
@@ -144,7 +146,7 @@ __device__ __forceinline__ void store_operand(uint8_t* qbuf, size_t plane_bytes,
 // (g, mb) = (b mod groups, b div groups): with 8 or 16 groups, round-robin dispatch
 // puts each group on one XCD.
 // ---------------------------------------------------------------------------------------
-template <int FORM, bool JLDS>
+template <int FORM, bool JLDS, bool DISC>
 __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   __shared__ int s_flag;
@@ -214,8 +216,7 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
     for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct)
-        store_operand<FORM>(a.q, plane_bytes, nks, row0 + rt * 16, col0 + ct * 16, lane,
-                            xs[rt][ct], a.discrete);
+        store_operand<FORM, DISC>(a.q, plane_bytes, nks, row0 + rt * 16, col0 + ct * 16, lane, xs[rt][ct]);
     alive = group_sync(ctr, (unsigned)a.nb, local, abort_flag, a.status, &s_flag);
   }
 
@@ -235,31 +236,61 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
       for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 
     if constexpr (FORM == kFormFP8) {
-      for (int ks = 0; ks < nks; ++ks) {
-        v8i bq[2];
+      // Software pipeline: Q fragments are fetched kPF k-steps ahead from L2 and J
+      // fragments one k-step ahead from LDS, so neither latency stalls the MFMA stream.
+      // nks is a multiple of kPF (np is padded to 512); the main loop prefetches
+      // unconditionally and the last kPF k-steps are peeled without loads.
+      constexpr int kPF = kKStepsUnroll;
+      v8i bq[kPF][2];
+      v8i aj[2][4];
+      auto load_b = [&](int ks, v8i* dst) {
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
           const unsigned base = (unsigned)(((rb0 + ct) * nks + ks) * 2048 + lane * 16);
           v4i lo = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kPolicySc1));
           v4i hi = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base + 1024, 0, kPolicySc1));
-          bq[ct] = cat(lo, hi);
+          dst[ct] = cat(lo, hi);
         }
-        v8i aj[4];
+      };
+      auto load_a = [&](int ks, v8i* dst) {
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
           const size_t o = (size_t)(rt * nks + ks) * 2048 + lane * 16;
           const uint8_t* pa = JLDS ? (lds + o) : (jrows + o);
-          aj[rt] = cat(*reinterpret_cast<const v4i*>(pa), *reinterpret_cast<const v4i*>(pa + 1024));
+          dst[rt] = cat(*reinterpret_cast<const v4i*>(pa), *reinterpret_cast<const v4i*>(pa + 1024));
         }
+      };
+      auto mfmas = [&](const v8i* aa, const v8i* bb) {
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
           for (int ct = 0; ct < 2; ++ct)
-            acc[rt][ct] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(aj[rt], bq[ct], acc[rt][ct],
-                                                                           0, 0, 0, 127, 0, 127);
+            acc[rt][ct] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(aa[rt], bb[ct], acc[rt][ct], 0, 0, 0,
+                                                                           127, 0, 127);
+      };
+#pragma unroll
+      for (int u = 0; u < kPF; ++u) load_b(u, bq[u]);
+      load_a(0, aj[0]);
+      int ks0 = 0;
+      for (; ks0 < nks - kPF; ks0 += kPF) {
+#pragma unroll
+        for (int u = 0; u < kPF; ++u) {
+          load_a(ks0 + u + 1, aj[(u + 1) & 1]);
+          __builtin_amdgcn_sched_barrier(0);  // keep each prefetch ahead of the MFMAs
+          mfmas(aj[u & 1], bq[u]);
+          load_b(ks0 + u + kPF, bq[u]);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kPF; ++u) {
+        if (u + 1 < kPF) load_a(ks0 + u + 1, aj[(u + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+        mfmas(aj[u & 1], bq[u]);
+        __builtin_amdgcn_sched_barrier(0);
       }
     } else if constexpr (FORM == kFormBF16X2) {
-      const int planes = a.discrete ? 1 : 2;  // sgn(x) has no low part
+      constexpr int planes = DISC ? 1 : 2;  // sgn(x) has no low part
       for (int ks = 0; ks < nks; ++ks) {
 #pragma unroll
         for (int sub = 0; sub < 4; ++sub) {
@@ -329,17 +360,16 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
           const float pxdt = px * dt;
           const float y1 = y - pxdt;      // y + dy
           const float gy = cdt * gsum;    // Dy = c dt sum_j J_ij q_j
-          float yn = y1 + gy;             // eq. (3)
+          const float yn = y1 + gy;       // eq. (3)
           const float dx = yn * dt;
-          float xn = x + dx;              // eq. (4)
-          if (__builtin_fabsf(xn) > 1.0f) {  // eq. (5)
-            xn = xn > 0.0f ? 1.0f : -1.0f;
-            yn = 0.0f;
-          }
-          xs[rt][ct][v] = xn; ys[rt][ct][v] = yn; ps[rt][ct][v] = pn;
+          const float xn = x + dx;        // eq. (4)
+          // eq. (5): beyond a wall x becomes sgn(x) (a clamp to [-1, 1]) and y becomes 0
+          const bool hit = __builtin_fabsf(xn) > 1.0f;
+          xs[rt][ct][v] = __builtin_amdgcn_fmed3f(xn, -1.0f, 1.0f);
+          ys[rt][ct][v] = hit ? 0.0f : yn;
+          ps[rt][ct][v] = pn;
         }
-        store_operand<FORM>(qnext, plane_bytes, nks, row0 + rt * 16, col0 + ct * 16, lane,
-                            xs[rt][ct], a.discrete);
+        store_operand<FORM, DISC>(qnext, plane_bytes, nks, row0 + rt * 16, col0 + ct * 16, lane, xs[rt][ct]);
       }
     alive = group_sync(ctr, (unsigned)((s + 2) * a.nb), local, abort_flag, a.status, &s_flag);
   }
@@ -531,17 +561,22 @@ inline int grid_for(size_t total, int block) {
   return (int)g;
 }
 
-template <int FORM, bool JLDS>
+template <int FORM, bool JLDS, bool DISC>
 const void* steps_kernel() {
-  return reinterpret_cast<const void*>(&k_steps<FORM, JLDS>);
+  return reinterpret_cast<const void*>(&k_steps<FORM, JLDS, DISC>);
 }
 
-const void* steps_kernel_for(int form, bool jlds) {
+template <bool DISC>
+const void* steps_kernel_disc(int form, bool jlds) {
   switch (form) {
-    case kFormFP8: return jlds ? steps_kernel<kFormFP8, true>() : steps_kernel<kFormFP8, false>();
-    case kFormBF16X2: return steps_kernel<kFormBF16X2, false>();
-    default: return steps_kernel<kFormFP32, false>();
+    case kFormFP8: return jlds ? steps_kernel<kFormFP8, true, DISC>() : steps_kernel<kFormFP8, false, DISC>();
+    case kFormBF16X2: return steps_kernel<kFormBF16X2, false, DISC>();
+    default: return steps_kernel<kFormFP32, false, DISC>();
   }
+}
+
+const void* steps_kernel_for(int form, bool jlds, bool discrete) {
+  return discrete ? steps_kernel_disc<true>(form, jlds) : steps_kernel_disc<false>(form, jlds);
 }
 
 size_t steps_lds_bytes(int form, bool jlds, int np) {
@@ -583,15 +618,20 @@ int max_coresident_workgroups(int form, bool jlds, int np) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  const void* k = steps_kernel_for(form, jlds);
-  const size_t lds = steps_lds_bytes(form, jlds, np);
-  if (lds > 0) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kThreads, lds) != hipSuccess) return 0;
-  return per_cu * cus;
+  int best = 0;
+  for (int disc = 0; disc < 2; ++disc) {
+    const void* k = steps_kernel_for(form, jlds, disc != 0);
+    const size_t lds = steps_lds_bytes(form, jlds, np);
+    if (lds > 0 && hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+      return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kThreads, lds) != hipSuccess) return 0;
+    best = disc == 0 ? per_cu * cus : std::min(best, per_cu * cus);
+  }
+  return best;
 }
 
 hipError_t launch_steps(int form, bool jlds, const StepArgs& a, hipStream_t stream) {
-  const void* k = steps_kernel_for(form, jlds);
+  const void* k = steps_kernel_for(form, jlds, a.discrete != 0);
   const size_t lds = steps_lds_bytes(form, jlds, a.np);
   if (lds > 0) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

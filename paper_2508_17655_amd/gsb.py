@@ -54,6 +54,13 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"libgsb.so is not built ({path}); run `python -m paper_2508_17655_amd.build`")
+    # PyTorch ships its own HIP runtime with the same soname as the system one.  Loading
+    # PyTorch first makes libgsb bind to that runtime, so streams and device memory handed
+    # over from PyTorch belong to the runtime the library calls.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, i32, u64, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t
     sig = {
