@@ -153,7 +153,7 @@ struct gsb_ctx {
   double A = 0, dt = 0;
   uint64_t seed = 0;
   int chunk_rp = 0;
-  bool jlds = false;
+  int kind = 0;
   std::vector<float> rtab_host;
   // device memory
   void* ws_user = nullptr;
@@ -192,32 +192,35 @@ struct Layout {
   int chunk_rp;
 };
 
-gsb_status plan(gsb_ctx* c, int R, int M, Layout* L, bool* jlds_out) {
+gsb_status plan(gsb_ctx* c, int R, int M, Layout* L, int* kind_out) {
   const int form = form_of(c->precision);
   const int np = c->np;
-  const int rp = (R + kBN - 1) / kBN * kBN;
-  const bool jlds = jlds_fits(form, np);
+  const int rp = (R + kRepPad - 1) / kRepPad * kRepPad;
+  const int kind = choose_kind(form, np);
+  const int bm = tile_rows_kind(kind), bn = tile_cols_kind(kind);
   int dev_count = 0;
   if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1)
     return fail(GSB_EDEVICE, "no HIP device");
-  const int max_wg = max_coresident_workgroups(form, jlds, np);
+  const int max_wg = max_coresident_workgroups(form, kind, np);
   if (max_wg < 1) return fail(GSB_EDEVICE, "occupancy query failed for the step kernel");
-  const int nb = np / kBM;
+  const int nb = np / bm;
   const int max_groups = max_wg / nb;
   if (max_groups < 1)
     return fail(GSB_EUNSUPPORTED, "n too large for one co-resident replica group on this device");
-  const int chunk_rp = std::min(rp, max_groups * kBN);
+  const int chunk_rp = std::min(rp, max_groups * bn / kRepPad * kRepPad);
+  if (chunk_rp < kRepPad)
+    return fail(GSB_EUNSUPPORTED, "n too large for one co-resident replica block on this device");
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
   L->j32 = take((size_t)np * np * 4);
-  L->jf = take((size_t)np * np * operand_elem_bytes(form));
+  L->jf = take((size_t)np * np * operand_elem_bytes(form));  // FP4 J uses half of it
   L->rtab = take((size_t)M * 4);
   L->X = take((size_t)rp * np * 4);
   L->Y = take((size_t)rp * np * 4);
   L->P = take((size_t)rp * np * 4);
   L->q_buf_bytes = (size_t)chunk_rp * np * operand_elem_bytes(form) * operand_planes(form);
   L->Q = take(2 * L->q_buf_bytes);
-  L->sync = take(sync_words(chunk_rp / kBN) * 4);
+  L->sync = take(sync_words(chunk_rp / bn) * 4);
   L->status = take(256);
   L->partial = take(energy_partial_doubles(np, rp) * 8);
   L->E = take((size_t)rp * 8);
@@ -225,7 +228,7 @@ gsb_status plan(gsb_ctx* c, int R, int M, Layout* L, bool* jlds_out) {
   L->spins = take((size_t)std::max(rp, 1) * c->n_user + 256);
   L->total = off;
   L->chunk_rp = chunk_rp;
-  *jlds_out = jlds;
+  *kind_out = kind;
   return GSB_OK;
 }
 
@@ -425,8 +428,8 @@ gsb_status gsb_workspace_size(gsb_ctx* c, int32_t replicas, int32_t steps, size_
   if (!c || !bytes) return fail(GSB_EINVAL, "NULL argument");
   if (replicas < 1 || steps < 1) return fail(GSB_EINVAL, "replicas and steps must be >= 1");
   Layout L;
-  bool jlds;
-  gsb_status s = plan(c, replicas, steps, &L, &jlds);
+  int kind;
+  gsb_status s = plan(c, replicas, steps, &L, &kind);
   if (s != GSB_OK) return s;
   *bytes = L.total;
   return GSB_OK;
@@ -462,13 +465,13 @@ gsb_status gsb_init(gsb_ctx* c, int32_t variant, int32_t schedule, double A, dou
     c->c = c->lmax > 0 ? 1.0 / c->lmax : 1.0;  // App. A: c = 1 / lambda_max
   }
   Layout L;
-  bool jlds;
-  gsb_status s = plan(c, replicas, steps, &L, &jlds);
+  int kind;
+  gsb_status s = plan(c, replicas, steps, &L, &kind);
   if (s != GSB_OK) return s;
   s = ensure_workspace(c, L.total);
   if (s != GSB_OK) return s;
   const int form = form_of(c->precision);
-  const int rp = (replicas + kBN - 1) / kBN * kBN;
+  const int rp = (replicas + kRepPad - 1) / kRepPad * kRepPad;
   // carve
   uint8_t* b = c->ws;
   const bool j32_moved = reinterpret_cast<float*>(b + L.j32) != c->j32;
@@ -490,7 +493,7 @@ gsb_status gsb_init(gsb_ctx* c, int32_t variant, int32_t schedule, double A, dou
   c->best_e = reinterpret_cast<double*>(b + L.best + 8);
   c->spins = reinterpret_cast<int8_t*>(b + L.spins);
   c->chunk_rp = L.chunk_rp;
-  c->jlds = jlds;
+  c->kind = kind;
   // instance upload and encode
   if (!c->j32_ready) {
     HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(c->j32), (size_t)c->np * c->np, 0u, c->stream), "clear J");
@@ -500,9 +503,11 @@ gsb_status gsb_init(gsb_ctx* c, int32_t variant, int32_t schedule, double A, dou
     c->j32_ready = true;
     c->jf_form = -1;
   }
-  if (c->jf_form != form) {
-    HIP_TRY(launch_encode_j(form, c->j32, c->np, c->jf, c->stream), "encode J");
-    c->jf_form = form;
+  const bool j_fp4 = kind != kKindGeneric;  // the FP8 kinds with J on chip keep J as FP4
+  const int jcode = form * 2 + (j_fp4 ? 1 : 0);
+  if (c->jf_form != jcode) {
+    HIP_TRY(launch_encode_j(form, j_fp4, c->j32, c->np, c->jf, c->stream), "encode J");
+    c->jf_form = jcode;
   }
   // schedule table r_m = 1 / (M - m) (eqs. (6), (7)), binary64 rounded once
   c->rtab_host.assign(steps, 0.0f);
@@ -547,8 +552,8 @@ gsb_status gsb_step(gsb_ctx* c, int32_t count) {
     a.n = c->n;
     a.np = c->np;
     a.rp = rcount;
-    a.groups = rcount / kBN;
-    a.nb = c->np / kBM;
+    a.groups = rcount / tile_cols_kind(c->kind);
+    a.nb = c->np / tile_rows_kind(c->kind);
     a.discrete = (c->variant == GSB_DSB || c->variant == GSB_GDSB) ? 1 : 0;
     a.m_begin = c->m;
     a.m_end = c->m + count;
@@ -565,7 +570,7 @@ gsb_status gsb_step(gsb_ctx* c, int32_t count) {
     a.sync = c->sync;
     a.status = c->status;
     HIP_TRY(launch_fill_u32(c->sync, sync_words(a.groups), 0u, c->stream), "clear sync");
-    HIP_TRY(launch_steps(form, c->jlds, a, c->stream), "step kernel launch");
+    HIP_TRY(launch_steps(form, c->kind, a, c->stream), "step kernel launch");
   }
   HIP_TRY(hipEventRecord(c->ev1, c->stream), "event record");
   c->timed = true;

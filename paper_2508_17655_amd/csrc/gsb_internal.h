@@ -7,9 +7,12 @@
 
 namespace gsb {
 
-// Tile geometry of the persistent step kernel (one workgroup per tile, 4 waves).
-constexpr int kBM = 64;        // rows of J (spins i) per workgroup
-constexpr int kBN = 128;       // replica columns per workgroup (4 waves x 32)
+// Tile geometry of the persistent step kernel: one workgroup of 4 waves per tile, each
+// wave a 64-spin x 32-replica tile.  With J resident in LDS (FP8 product, J stored as
+// FP4) a workgroup is 128 spins x 64 replicas; otherwise 64 spins x 128 replicas.
+constexpr int kWaveRows = 64;
+constexpr int kWaveCols = 32;
+constexpr int kRepPad = 128;   // replica counts are padded to a multiple of this
 constexpr int kKS = 128;       // K (spins j) per k-step
 constexpr int kThreads = 256;
 constexpr int kKStepsUnroll = 4;  // k-steps per software-pipeline round
@@ -17,19 +20,30 @@ constexpr int kRowPad = kKS * kKStepsUnroll;  // np is a multiple of this (512)
 
 enum Form { kFormFP32 = 0, kFormBF16X2 = 1, kFormFP8 = 2 };
 
+// Step-kernel variants.
+//   kKindRegJ : FP8 product, np <= 2048: J rows in registers (FP4), 256 spins x 32 replicas
+//               per workgroup, two half-step-offset column sub-groups.
+//   kKindGeneric : J fragments from L2 (any form), 64 spins x 128 replicas per workgroup.
+enum Kind { kKindGeneric = 0, kKindRegJ = 2 };
+
+__host__ __device__ constexpr int tile_rows_kind(int kind) { return kind == kKindRegJ ? 256 : 64; }
+__host__ __device__ constexpr int tile_cols_kind(int kind) { return 8192 / tile_rows_kind(kind); }
+
 // Bytes of one operand plane per (16-replica block, k-step) and of one J block per
-// (16-row tile, k-step), in the fragment-major layouts.
+// (16-row tile, k-step), in the fragment-major layouts.  (The register-resident FP8 path
+// stores J as FP4 (E2M1), 1 KiB per block, which holds 0 and +-1 exactly.)
 __host__ __device__ constexpr size_t operand_block_bytes(int form) {
   return form == kFormFP8 ? 2048 : (form == kFormBF16X2 ? 4096 : 8192);
 }
+
 __host__ __device__ constexpr int operand_planes(int form) { return form == kFormBF16X2 ? 2 : 1; }
 
 struct StepArgs {
   int n;          // spins carried by the dynamics (including an ancilla)
   int np;         // padded spins (multiple of kRowPad)
   int rp;         // replicas of this launch (multiple of kBN)
-  int groups;     // rp / kBN
-  int nb;         // np / kBM  (workgroups per replica group)
+  int groups;     // rp / tile_cols
+  int nb;         // np / tile_rows  (workgroups per replica group)
   int discrete;   // 1: operand is sgn(x) (dSB, GdSB)
   int m_begin, m_end;
   float A, dt, cdt;
@@ -42,17 +56,17 @@ struct StepArgs {
   unsigned* status;       // set nonzero on a device-side timeout
 };
 
-inline size_t sync_words(int groups) { return (size_t)(3 * groups + 1) * 64; }
+inline size_t sync_words(int groups) { return (size_t)(4 * groups + 1) * 64; }
 
 // ---- launchers (all asynchronous on `stream`) ----
 hipError_t launch_fill_u32(unsigned* p, size_t count, unsigned v, hipStream_t stream);
-hipError_t launch_encode_j(int form, const float* j32, int np, void* jf, hipStream_t stream);
+hipError_t launch_encode_j(int form, bool fp4, const float* j32, int np, void* jf, hipStream_t stream);
 hipError_t launch_init_state(int n, int np, int rp, uint64_t seed, int mode, float* x, float* y,
                              float* p, hipStream_t stream);
-// Persistent step kernel.  `jlds` selects the LDS-resident J variant (FP8 only).
-hipError_t launch_steps(int form, bool jlds, const StepArgs& a, hipStream_t stream);
-int max_coresident_workgroups(int form, bool jlds, int np);
-bool jlds_fits(int form, int np);
+// Persistent step kernel of variant `kind` (see Kind).
+hipError_t launch_steps(int form, int kind, const StepArgs& a, hipStream_t stream);
+int max_coresident_workgroups(int form, int kind, int np);
+int choose_kind(int form, int np);
 hipError_t launch_energy(const float* j32, int n, int np, int rp, int r_count, const float* x,
                          double* partial, double* energies, hipStream_t stream);
 size_t energy_partial_doubles(int np, int rp);

@@ -139,24 +139,28 @@ __device__ __forceinline__ void store_operand(uint8_t* qbuf, size_t plane_bytes,
 }
 
 // ---------------------------------------------------------------------------------------
-// Persistent step kernel.  Workgroup (g, mb) owns spins [64 mb, 64 mb + 64) of replicas
-// [128 g, 128 g + 128); wave w owns replica columns [32 w, 32 w + 32) of that range, so
-// each wave computes a 64 x 32 tile of G = J Q (4 x 2 MFMA tiles of 16 x 16) and keeps
-// x, y, p of those 2048 elements in registers for the whole launch.  Workgroup b is
-// (g, mb) = (b mod groups, b div groups): with 8 or 16 groups, round-robin dispatch
+// Generic persistent step kernel (any product form; J fragments read from L2).
+// Workgroup (g, mb) owns spins [64 mb, 64 mb + 64) of replicas [128 g, 128 g + 128); each
+// of its 4 waves computes a 64 x 32 tile of G = J Q (4 x 2 MFMA tiles of 16 x 16) and
+// keeps x, y, p of those 2048 elements in registers for the whole launch.  Workgroup b
+// is (g, mb) = (b mod groups, b div groups): with 8 or 16 groups, round-robin dispatch
 // puts each group on one XCD.
 // ---------------------------------------------------------------------------------------
-template <int FORM, bool JLDS, bool DISC>
+template <int FORM, bool DISC>
 __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
-  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   __shared__ int s_flag;
   __shared__ int s_local;
+  constexpr int BM = tile_rows_kind(kKindGeneric);
+  constexpr int BN = tile_cols_kind(kKindGeneric);
+  constexpr int WCOLS = BN / kWaveCols;  // waves across the replica columns
+  constexpr int kQPolicy = kPolicySc1;   // each wave reads its own columns: skip L1
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = blockIdx.x % a.groups;
   const int mb = blockIdx.x / a.groups;
-  const int row0 = mb * kBM;
-  const int col0 = g * kBN + wave * 32;
+  const int wrow = wave / WCOLS;             // 64-row slice of the workgroup's rows
+  const int row0 = mb * BM + wrow * kWaveRows;
+  const int col0 = g * BN + (wave % WCOLS) * kWaveCols;
   const int nks = a.np / kKS;
   unsigned* ctr = a.sync + (size_t)g * 64;
   unsigned* hs = a.sync + (size_t)(a.groups + g) * 64;
@@ -165,13 +169,8 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
   const size_t jblk = operand_block_bytes(FORM);
   const size_t plane_bytes = a.q_buf_bytes / operand_planes(FORM);
 
-  // J rows of this workgroup: 4 row tiles x nks k-steps, contiguous in the layout.
-  const uint8_t* jrows = static_cast<const uint8_t*>(a.jf) + (size_t)(row0 >> 4) * nks * jblk;
-  if constexpr (JLDS) {
-    const int total = 4 * nks * (int)(jblk / 16);
-    const v4u* src = reinterpret_cast<const v4u*>(jrows);
-    for (int t = tid; t < total; t += kThreads) reinterpret_cast<v4u*>(lds)[t] = src[t];
-  }
+  // J rows of this wave: 4 row tiles x nks k-steps, contiguous in the layout.
+  const uint8_t* jrows = static_cast<const uint8_t*>(a.jf) + (size_t)(mb * BM / 16 + 4 * wrow) * nks * jblk;
 
   // State of this wave's 64 x 32 tile: lane holds rows 4*(lane/16)+v of column lane%16.
   float xs[4][2][4], ys[4][2][4], ps[4][2][4];
@@ -247,16 +246,15 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
           const unsigned base = (unsigned)(((rb0 + ct) * nks + ks) * 2048 + lane * 16);
-          v4i lo = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kPolicySc1));
-          v4i hi = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base + 1024, 0, kPolicySc1));
+          v4i lo = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kQPolicy));
+          v4i hi = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base + 1024, 0, kQPolicy));
           dst[ct] = cat(lo, hi);
         }
       };
       auto load_a = [&](int ks, v8i* dst) {
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
-          const size_t o = (size_t)(rt * nks + ks) * 2048 + lane * 16;
-          const uint8_t* pa = JLDS ? (lds + o) : (jrows + o);
+          const uint8_t* pa = jrows + (size_t)(rt * nks + ks) * 2048 + lane * 16;
           dst[rt] = cat(*reinterpret_cast<const v4i*>(pa), *reinterpret_cast<const v4i*>(pa + 1024));
         }
       };
@@ -388,6 +386,261 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------------------
+// Register-resident step kernel for the FP8 product with np <= 2048 (NKS = np/128 k-steps).
+//
+// Workgroup (g, mb) owns spins [256 mb, 256 mb + 256) of replicas [32 g, 32 g + 32); wave
+// w owns the 64 spins [256 mb + 64 w, +64) and keeps its 64 rows of J, as FP4 (exact for
+// 0 and +-1), in registers for the whole launch (4 row tiles x NKS fragments of 16 bytes
+// per lane: 256 registers at np = 2048).  The four waves read the same Q fragments, which
+// come through L1.
+//
+// The 32 replica columns form two independent sub-groups of 16 (column tiles 0 and 1),
+// each with its own barrier counter, processed half a step apart:
+//   K loop (sub 0) | wait (sub 1) + first Q loads of sub 1 | update (sub 0), publish, arrive
+//   K loop (sub 1) | wait (sub 0, next step) + first loads | update (sub 1), publish, arrive
+// so every wait comes half a step after the arrivals it needs, and the first operand loads
+// of each K loop are in flight during the preceding update.
+// ---------------------------------------------------------------------------------------
+template <int NKS, bool DISC>
+__global__ void __launch_bounds__(kThreads, 1) k_steps_rj(StepArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  __shared__ int s_flag;
+  __shared__ int s_local;
+  constexpr int kPF = kKStepsUnroll;
+  static_assert(NKS % kPF == 0 && NKS >= kPF, "k-steps must be a multiple of the prefetch depth");
+  // k-steps [0, NREG) of J live in registers, [NREG, NKS) in LDS (register budget: J,
+  // the state of 2048 elements, the accumulators and the operand prefetch share 512)
+  constexpr int NREG = NKS > 12 ? 12 : NKS;
+  constexpr int NLDS = NKS - NREG;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = blockIdx.x % a.groups;
+  const int mb = blockIdx.x / a.groups;
+  const int row0 = mb * 256 + wave * kWaveRows;
+  const int col0 = g * kWaveCols;
+  unsigned* ctr0 = a.sync + (size_t)(2 * g) * 64;
+  unsigned* ctr1 = a.sync + (size_t)(2 * g + 1) * 64;
+  unsigned* hs = a.sync + (size_t)(2 * a.groups + g) * 64;
+  unsigned* msk = a.sync + (size_t)(3 * a.groups + g) * 64;
+  unsigned* abort_flag = a.sync + (size_t)(4 * a.groups) * 64;
+
+  // J rows of this wave (FP4 fragment-major, 1 KiB per (row tile, k-step)).
+  v4i jr[4][NREG];
+  uint8_t* jl = lds + (size_t)wave * 4 * (NLDS > 0 ? NLDS : 1) * 1024 + lane * 16;  // [rt][ks - NREG][lane]
+  {
+    const uint8_t* jw = static_cast<const uint8_t*>(a.jf) + (size_t)(row0 >> 4) * NKS * 1024 + lane * 16;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
+        const v4i f = *reinterpret_cast<const v4i*>(jw + (size_t)(rt * NKS + ks) * 1024);
+        if (ks < NREG) jr[rt][ks < NREG ? ks : 0] = f;
+        else *reinterpret_cast<v4i*>(jl + (size_t)(rt * NLDS + (ks - NREG)) * 1024) = f;
+      }
+  }
+  v4i jt[2][4];  // LDS part, double-buffered one k-step ahead
+  auto load_jt = [&](int ks, v4i* dst) {
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) dst[rt] = *reinterpret_cast<const v4i*>(jl + (size_t)(rt * NLDS + (ks - NREG)) * 1024);
+  };
+
+  // State: [sub-group = column tile][row tile][v]; lane holds rows 4*(lane/16)+v of column
+  // lane%16 of each 16 x 16 tile.
+  float xs[2][4][4], ys[2][4][4], ps[2][4][4];
+#pragma unroll
+  for (int sub = 0; sub < 2; ++sub)
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      const int i = row0 + rt * 16 + 4 * (lane >> 4);
+      const int r = col0 + sub * 16 + (lane & 15);
+      const size_t o = (size_t)r * a.np + i;
+      const v4f vx = *reinterpret_cast<const v4f*>(a.x + o);
+      const v4f vy = *reinterpret_cast<const v4f*>(a.y + o);
+      const v4f vp = *reinterpret_cast<const v4f*>(a.p + o);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) { xs[sub][rt][v] = vx[v]; ys[sub][rt][v] = vy[v]; ps[sub][rt][v] = vp[v]; }
+    }
+
+  // Handshake: learn whether all members of this group run on one XCD.
+  if (tid == 0) {
+    const unsigned xcc = (unsigned)__builtin_amdgcn_s_getreg(kHwRegXccId) & 15u;
+    __hip_atomic_fetch_or(msk, 1u << xcc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(hs, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    unsigned spins = 0;
+    while (ld_dev(hs) < (unsigned)a.nb) {
+      ++spins;
+      if ((spins & 63u) == 0 && ld_dev(abort_flag)) { ok = 0; break; }
+      if (spins > kSpinLimit) { st_dev(abort_flag, 1u); st_dev(a.status, 1u); ok = 0; break; }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    s_local = (__builtin_popcount(ld_dev(msk)) == 1) ? 1 : 0;
+    s_flag = ok;
+  }
+  __syncthreads();
+  bool alive = s_flag != 0;
+  const int local = s_local;
+
+  // arrive: this workgroup's operand stores for `ctr` are complete and counted.
+  auto arrive = [&](unsigned* ctr) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) {
+      if (!local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  };
+  // wait: every member has arrived `target` times on `ctr`; then this CU's L1 holds no
+  // stale copy of the operand buffer (it is invalidated), so plain loads see the data.
+  // `seen` is a count read earlier (mid K loop); when it already reaches the target the
+  // poll round trip is skipped.
+  auto wait = [&](unsigned* ctr, unsigned target, unsigned seen) -> bool {
+    if (tid == 0) {
+      int ok = 1;
+      unsigned spins = 0;
+      unsigned v = seen;
+      while (v < target) {
+        v = ld_dev(ctr);
+        ++spins;
+        if ((spins & 63u) == 0 && ld_dev(abort_flag)) { ok = 0; break; }
+        if (spins > kSpinLimit) { st_dev(abort_flag, 1u); st_dev(a.status, 1u); ok = 0; break; }
+      }
+      if (!local) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      } else {
+        asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+      }
+      s_flag = ok;
+    }
+    __syncthreads();
+    return s_flag != 0;
+  };
+
+  const __amdgpu_buffer_rsrc_t qr = make_rsrc(a.q, 2 * a.q_buf_bytes);
+  v8i bq[kPF];
+  // Q fragment of column tile `sub`, k-step ks, in ping-pong buffer `buf`.
+  auto load_b = [&](int sub, int buf, int ks, v8i& dst) {
+    const unsigned base = (unsigned)((size_t)buf * a.q_buf_bytes) +
+                          (unsigned)(((2 * g + sub) * NKS + ks) * 2048 + lane * 16);
+    const v4i lo = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, 0));
+    const v4i hi = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base + 1024, 0, 0));
+    dst = cat(lo, hi);
+  };
+  auto prefetch = [&](int sub, int buf) {
+#pragma unroll
+    for (int u = 0; u < kPF; ++u) load_b(sub, buf, u, bq[u]);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+  };
+
+  const float A = a.A, dt = a.dt, cdt = a.cdt;
+  // update of column tile `sub` with the product in acc, then its operand for the next step
+  auto update = [&](int sub, const v4f* acc, float rm, uint8_t* qnext) {
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float x = xs[sub][rt][v], y = ys[sub][rt][v], p = ps[sub][rt][v];
+        const float gsum = acc[rt][v];
+        const float xx = x * x;
+        const float ax = A * xx;
+        const float f = 1.0f - ax;
+        const float fp = f * p;
+        const float dp = fp * rm;
+        const float pn = p - dp;        // p_i(t_{m+1}), eq. (7)
+        const float px = pn * x;
+        const float pxdt = px * dt;
+        const float y1 = y - pxdt;      // y + dy
+        const float gy = cdt * gsum;    // Dy = c dt sum_j J_ij q_j
+        const float yn = y1 + gy;       // eq. (3)
+        const float dx = yn * dt;
+        const float xn = x + dx;        // eq. (4)
+        const bool hit = __builtin_fabsf(xn) > 1.0f;  // eq. (5)
+        xs[sub][rt][v] = __builtin_amdgcn_fmed3f(xn, -1.0f, 1.0f);
+        ys[sub][rt][v] = hit ? 0.0f : yn;
+        ps[sub][rt][v] = pn;
+      }
+      store_operand<kFormFP8, DISC>(qnext, a.q_buf_bytes, NKS, row0 + rt * 16, col0 + sub * 16, lane,
+                                    xs[sub][rt]);
+    }
+  };
+
+  // Operand of the starting state for both column tiles, then the first arrivals.
+  if (alive) {
+#pragma unroll
+    for (int sub = 0; sub < 2; ++sub)
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+        store_operand<kFormFP8, DISC>(a.q, a.q_buf_bytes, NKS, row0 + rt * 16, col0 + sub * 16, lane,
+                                      xs[sub][rt]);
+    arrive(ctr0);
+    arrive(ctr1);
+    alive = wait(ctr0, (unsigned)a.nb, 0u);
+    if (alive) prefetch(0, 0);
+  }
+
+  const int steps = a.m_end - a.m_begin;
+  for (int s = 0; alive && s < steps; ++s) {
+    const int m = a.m_begin + s;
+    const int cur = s & 1;
+    uint8_t* qnext = a.q + (size_t)(cur ^ 1) * a.q_buf_bytes;
+    const float rm = a.rtab[m];
+#pragma unroll
+    for (int sub = 0; sub < 2; ++sub) {
+      unsigned seen = 0;  // count of the other column tile's counter, read mid K loop
+      unsigned* const other = sub == 0 ? ctr1 : ctr0;
+      v4f acc[4];
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) acc[rt] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
+        if (ks + 1 >= NREG && ks + 1 < NKS) load_jt(ks + 1, jt[(ks + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+          const v4i f = ks < NREG ? jr[rt][ks < NREG ? ks : 0] : jt[ks & 1][rt];
+          acc[rt] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(cat(f, f), bq[ks % kPF], acc[rt], 4, 0, 0,
+                                                                     127, 0, 127);
+        }
+        // Pin this k-step's MFMAs here: the empty asm reads and redefines the accumulators
+        // and, being volatile, keeps its place relative to the memory fences around the
+        // prefetches, so loads and MFMAs stay interleaved as written.
+        asm volatile("" : "+a"(acc[0]), "+a"(acc[1]), "+a"(acc[2]), "+a"(acc[3]));
+        if (ks + kPF < NKS) load_b(sub, cur, ks + kPF, bq[ks % kPF]);
+        if (ks == NKS / 2 && tid == 0) seen = ld_dev(other);
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      // wait for the other column tile's data and start its first loads
+      if (sub == 0) {
+        alive = wait(ctr1, (unsigned)((s + 1) * a.nb), seen);
+        if (alive) prefetch(1, cur);
+      } else if (s + 1 < steps) {
+        alive = wait(ctr0, (unsigned)((s + 2) * a.nb), seen);
+        if (alive) prefetch(0, cur ^ 1);
+      }
+      if (!alive) break;
+      update(sub, acc, rm, qnext);
+      arrive(sub == 0 ? ctr0 : ctr1);
+    }
+  }
+
+#pragma unroll
+  for (int sub = 0; sub < 2; ++sub)
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      const int i = row0 + rt * 16 + 4 * (lane >> 4);
+      const int r = col0 + sub * 16 + (lane & 15);
+      const size_t o = (size_t)r * a.np + i;
+      *reinterpret_cast<v4f*>(a.x + o) = v4f{xs[sub][rt][0], xs[sub][rt][1], xs[sub][rt][2], xs[sub][rt][3]};
+      *reinterpret_cast<v4f*>(a.y + o) = v4f{ys[sub][rt][0], ys[sub][rt][1], ys[sub][rt][2], ys[sub][rt][3]};
+      *reinterpret_cast<v4f*>(a.p + o) = v4f{ps[sub][rt][0], ps[sub][rt][1], ps[sub][rt][2], ps[sub][rt][3]};
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // Small kernels.
 // ---------------------------------------------------------------------------------------
 __global__ void k_fill_u32(unsigned* p, size_t count, unsigned v) {
@@ -417,6 +670,34 @@ __global__ void k_encode_j(const float* j32, int np, uint8_t* jf) {
       const size_t off = ((size_t)(rt * nks + kc) * 8 + (kk >> 4)) * 1024 + lanep * 16 + (kk & 3) * 4;
       *reinterpret_cast<float*>(jf + off) = v;
     }
+  }
+}
+
+// J (zero padded, entries in {0, +-1}) -> FP4 (E2M1) fragment-major layout of the
+// register-resident FP8 path: [row tile][k-step][lane 64][16 bytes], two values per byte,
+// low nibble first.  In the mixed FP4 x FP8 MFMA (16x16x128), FP8 byte j of lane group g
+// multiplies FP4 nibble p of the same row/column lanes with p = 16 g + j for j < 16 and
+// p = 64 + 16 g + (j - 16) for j >= 16 (p counts nibbles over the four lane groups,
+// 32 per group).  The FP8 operand layout puts k-step offset kk = 32 g + j at byte j of
+// lane group g, so nibble p must hold kk(p) below.
+__device__ __forceinline__ int fp4_pair_kk(int p) {
+  return p < 64 ? 32 * (p >> 4) + (p & 15) : 32 * ((p - 64) >> 4) + 16 + ((p - 64) & 15);
+}
+__device__ __forceinline__ unsigned fp4_code(float v) {  // exact for 0 and +-1
+  return (v < 0.0f ? 0x8u : 0u) | (__builtin_fabsf(v) == 1.0f ? 0x2u : 0u);
+}
+__global__ void k_encode_j4(const float* j32, int np, uint8_t* jf) {
+  const size_t total = (size_t)np * np / 2;
+  const int nks = np / kKS;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+    const size_t blk = t >> 10;
+    const int lane = (int)((t >> 4) & 63), b = (int)(t & 15);
+    const int rt = (int)(blk / nks), kc = (int)(blk % nks);
+    const int i = rt * 16 + (lane & 15);
+    const int p0 = 32 * (lane >> 4) + 2 * b;
+    const float v0 = j32[(size_t)i * np + kc * kKS + fp4_pair_kk(p0)];
+    const float v1 = j32[(size_t)i * np + kc * kKS + fp4_pair_kk(p0 + 1)];
+    jf[t] = (uint8_t)(fp4_code(v0) | (fp4_code(v1) << 4));
   }
 }
 
@@ -561,26 +842,38 @@ inline int grid_for(size_t total, int block) {
   return (int)g;
 }
 
-template <int FORM, bool JLDS, bool DISC>
+template <int FORM, bool DISC>
 const void* steps_kernel() {
-  return reinterpret_cast<const void*>(&k_steps<FORM, JLDS, DISC>);
+  return reinterpret_cast<const void*>(&k_steps<FORM, DISC>);
 }
 
 template <bool DISC>
-const void* steps_kernel_disc(int form, bool jlds) {
+const void* steps_kernel_disc(int form, int kind, int np) {
+  if (kind == kKindRegJ) {
+    switch (np / kKS) {
+      case 4: return reinterpret_cast<const void*>(&k_steps_rj<4, DISC>);
+      case 8: return reinterpret_cast<const void*>(&k_steps_rj<8, DISC>);
+      case 12: return reinterpret_cast<const void*>(&k_steps_rj<12, DISC>);
+      case 16: return reinterpret_cast<const void*>(&k_steps_rj<16, DISC>);
+      default: return nullptr;
+    }
+  }
   switch (form) {
-    case kFormFP8: return jlds ? steps_kernel<kFormFP8, true, DISC>() : steps_kernel<kFormFP8, false, DISC>();
-    case kFormBF16X2: return steps_kernel<kFormBF16X2, false, DISC>();
-    default: return steps_kernel<kFormFP32, false, DISC>();
+    case kFormFP8: return steps_kernel<kFormFP8, DISC>();
+    case kFormBF16X2: return steps_kernel<kFormBF16X2, DISC>();
+    default: return steps_kernel<kFormFP32, DISC>();
   }
 }
 
-const void* steps_kernel_for(int form, bool jlds, bool discrete) {
-  return discrete ? steps_kernel_disc<true>(form, jlds) : steps_kernel_disc<false>(form, jlds);
+const void* steps_kernel_for(int form, int kind, int np, bool discrete) {
+  return discrete ? steps_kernel_disc<true>(form, kind, np) : steps_kernel_disc<false>(form, kind, np);
 }
 
-size_t steps_lds_bytes(int form, bool jlds, int np) {
-  return jlds ? (size_t)4 * (np / kKS) * operand_block_bytes(form) : 0;
+size_t steps_lds_bytes(int form, int kind, int np) {
+  (void)form;
+  const int nks = np / kKS;
+  if (kind == kKindRegJ) return nks > 12 ? (size_t)4 * 4 * (nks - 12) * 1024 : 0;
+  return 0;
 }
 
 }  // namespace
@@ -593,11 +886,13 @@ hipError_t launch_fill_u32(unsigned* p, size_t count, unsigned v, hipStream_t st
   return hipGetLastError();
 }
 
-hipError_t launch_encode_j(int form, const float* j32, int np, void* jf, hipStream_t stream) {
+hipError_t launch_encode_j(int form, bool fp4, const float* j32, int np, void* jf, hipStream_t stream) {
   const size_t total = (size_t)np * np;
   const dim3 grid(grid_for(total, 256)), block(256);
   uint8_t* out = static_cast<uint8_t*>(jf);
-  if (form == kFormFP8) hipLaunchKernelGGL(k_encode_j<kFormFP8>, grid, block, 0, stream, j32, np, out);
+  if (form == kFormFP8 && fp4)
+    hipLaunchKernelGGL(k_encode_j4, dim3(grid_for(total / 2, 256)), block, 0, stream, j32, np, out);
+  else if (form == kFormFP8) hipLaunchKernelGGL(k_encode_j<kFormFP8>, grid, block, 0, stream, j32, np, out);
   else if (form == kFormBF16X2) hipLaunchKernelGGL(k_encode_j<kFormBF16X2>, grid, block, 0, stream, j32, np, out);
   else hipLaunchKernelGGL(k_encode_j<kFormFP32>, grid, block, 0, stream, j32, np, out);
   return hipGetLastError();
@@ -610,18 +905,19 @@ hipError_t launch_init_state(int n, int np, int rp, uint64_t seed, int mode, flo
   return hipGetLastError();
 }
 
-bool jlds_fits(int form, int np) {
-  return form == kFormFP8 && steps_lds_bytes(form, true, np) <= 160 * 1024 - 64;
+int choose_kind(int form, int np) {
+  return (form == kFormFP8 && np <= 2048) ? kKindRegJ : kKindGeneric;
 }
 
-int max_coresident_workgroups(int form, bool jlds, int np) {
+int max_coresident_workgroups(int form, int kind, int np) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   int best = 0;
   for (int disc = 0; disc < 2; ++disc) {
-    const void* k = steps_kernel_for(form, jlds, disc != 0);
-    const size_t lds = steps_lds_bytes(form, jlds, np);
+    const void* k = steps_kernel_for(form, kind, np, disc != 0);
+    if (!k) return 0;
+    const size_t lds = steps_lds_bytes(form, kind, np);
     if (lds > 0 && hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
       return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kThreads, lds) != hipSuccess) return 0;
@@ -630,9 +926,10 @@ int max_coresident_workgroups(int form, bool jlds, int np) {
   return best;
 }
 
-hipError_t launch_steps(int form, bool jlds, const StepArgs& a, hipStream_t stream) {
-  const void* k = steps_kernel_for(form, jlds, a.discrete != 0);
-  const size_t lds = steps_lds_bytes(form, jlds, a.np);
+hipError_t launch_steps(int form, int kind, const StepArgs& a, hipStream_t stream) {
+  const void* k = steps_kernel_for(form, kind, a.np, a.discrete != 0);
+  if (!k) return hipErrorInvalidValue;
+  const size_t lds = steps_lds_bytes(form, kind, a.np);
   if (lds > 0) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
