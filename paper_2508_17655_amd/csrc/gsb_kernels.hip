@@ -29,6 +29,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 constexpr int kPolicySc1 = 16;             // buffer-load cache policy: device scope (skips L1)
+constexpr int kRegKSteps = 8;              // k-steps of J kept in registers by k_steps_rj
 constexpr unsigned kSpinLimit = 1u << 22;  // polls before a barrier gives up (seconds)
 constexpr int kHwRegXccId = 20 | (0 << 6) | ((4 - 1) << 11);  // hwreg(HW_REG_XCC_ID, 0, 4)
 
@@ -402,7 +403,7 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
 // of each K loop are in flight during the preceding update.
 // ---------------------------------------------------------------------------------------
 template <int NKS, bool DISC>
-__global__ void __launch_bounds__(kThreads, 1) k_steps_rj(StepArgs a) {
+__global__ void __launch_bounds__(kThreads, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) k_steps_rj(StepArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   __shared__ int s_flag;
   __shared__ int s_local;
@@ -410,7 +411,7 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps_rj(StepArgs a) {
   static_assert(NKS % kPF == 0 && NKS >= kPF, "k-steps must be a multiple of the prefetch depth");
   // k-steps [0, NREG) of J live in registers, [NREG, NKS) in LDS (register budget: J,
   // the state of 2048 elements, the accumulators and the operand prefetch share 512)
-  constexpr int NREG = NKS > 12 ? 12 : NKS;
+  constexpr int NREG = NKS > kRegKSteps ? kRegKSteps : NKS;
   constexpr int NLDS = NKS - NREG;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -536,35 +537,46 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps_rj(StepArgs a) {
   };
 
   const float A = a.A, dt = a.dt, cdt = a.cdt;
-  // update of column tile `sub` with the product in acc, then its operand for the next step
+  // Update of column tile `sub` with the product in acc (eqs. (7), (3), (4), (5), binary32,
+  // one rounding per operator), then its operand for the next step.  Written stage by
+  // stage over the 16 elements of the tile so that each stage is 16 independent operations.
   auto update = [&](int sub, const v4f* acc, float rm, uint8_t* qnext) {
+    float t[16], u[16];
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
+    for (int e = 0; e < 16; ++e) { const float x = xs[sub][e >> 2][e & 3]; t[e] = x * x; }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const float x = xs[sub][rt][v], y = ys[sub][rt][v], p = ps[sub][rt][v];
-        const float gsum = acc[rt][v];
-        const float xx = x * x;
-        const float ax = A * xx;
-        const float f = 1.0f - ax;
-        const float fp = f * p;
-        const float dp = fp * rm;
-        const float pn = p - dp;        // p_i(t_{m+1}), eq. (7)
-        const float px = pn * x;
-        const float pxdt = px * dt;
-        const float y1 = y - pxdt;      // y + dy
-        const float gy = cdt * gsum;    // Dy = c dt sum_j J_ij q_j
-        const float yn = y1 + gy;       // eq. (3)
-        const float dx = yn * dt;
-        const float xn = x + dx;        // eq. (4)
-        const bool hit = __builtin_fabsf(xn) > 1.0f;  // eq. (5)
-        xs[sub][rt][v] = __builtin_amdgcn_fmed3f(xn, -1.0f, 1.0f);
-        ys[sub][rt][v] = hit ? 0.0f : yn;
-        ps[sub][rt][v] = pn;
-      }
+    for (int e = 0; e < 16; ++e) t[e] = A * t[e];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t[e] = 1.0f - t[e];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t[e] = t[e] * ps[sub][e >> 2][e & 3];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t[e] = t[e] * rm;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) ps[sub][e >> 2][e & 3] = ps[sub][e >> 2][e & 3] - t[e];  // p(t_{m+1})
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t[e] = ps[sub][e >> 2][e & 3] * xs[sub][e >> 2][e & 3];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t[e] = t[e] * dt;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t[e] = ys[sub][e >> 2][e & 3] - t[e];            // y + dy
+#pragma unroll
+    for (int e = 0; e < 16; ++e) u[e] = cdt * acc[e >> 2][e & 3];                 // Dy
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t[e] = t[e] + u[e];                              // eq. (3)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) u[e] = t[e] * dt;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) u[e] = xs[sub][e >> 2][e & 3] + u[e];            // eq. (4)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {                                                // eq. (5)
+      ys[sub][e >> 2][e & 3] = __builtin_fabsf(u[e]) > 1.0f ? 0.0f : t[e];
+      xs[sub][e >> 2][e & 3] = __builtin_amdgcn_fmed3f(u[e], -1.0f, 1.0f);
+    }
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
       store_operand<kFormFP8, DISC>(qnext, a.q_buf_bytes, NKS, row0 + rt * 16, col0 + sub * 16, lane,
                                     xs[sub][rt]);
-    }
   };
 
   // Operand of the starting state for both column tiles, then the first arrivals.
@@ -872,7 +884,7 @@ const void* steps_kernel_for(int form, int kind, int np, bool discrete) {
 size_t steps_lds_bytes(int form, int kind, int np) {
   (void)form;
   const int nks = np / kKS;
-  if (kind == kKindRegJ) return nks > 12 ? (size_t)4 * 4 * (nks - 12) * 1024 : 0;
+  if (kind == kKindRegJ) return nks > kRegKSteps ? (size_t)4 * 4 * (nks - kRegKSteps) * 1024 : 0;
   return 0;
 }
 
