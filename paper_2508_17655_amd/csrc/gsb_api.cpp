@@ -244,10 +244,13 @@ gsb_status ensure_workspace(gsb_ctx* c, size_t need) {
   } else {
     if (c->ws_own_bytes < need) {
       if (c->ws_own) {
-        hipStreamSynchronize(c->stream);
-        hipFree(c->ws_own);
+        const hipError_t es = hipStreamSynchronize(c->stream);
+        const hipError_t ef = hipFree(c->ws_own);
         c->ws_own = nullptr;
         c->ws_own_bytes = 0;
+        if (es != hipSuccess || ef != hipSuccess)
+          return fail(GSB_EDEVICE, std::string("releasing the old workspace: ") +
+                                       hipGetErrorString(es != hipSuccess ? es : ef));
       }
       void* p = nullptr;
       if (hipMalloc(&p, need) != hipSuccess)
@@ -346,12 +349,13 @@ gsb_status gsb_create(const float* J, const float* h, int32_t n, gsb_ctx** out) 
 
 void gsb_destroy(gsb_ctx* c) {
   if (!c) return;
+  // Teardown cannot report errors; a failed synchronisation or free is ignored here.
   if (c->ws_own) {
-    hipStreamSynchronize(c->stream);
-    hipFree(c->ws_own);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->ws_own);
   }
-  if (c->ev0) hipEventDestroy(c->ev0);
-  if (c->ev1) hipEventDestroy(c->ev1);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
   delete c;
 }
 

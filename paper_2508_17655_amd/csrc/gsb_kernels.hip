@@ -29,7 +29,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 constexpr int kPolicySc1 = 16;             // buffer-load cache policy: device scope (skips L1)
-constexpr int kRegKSteps = 8;              // k-steps of J kept in registers by k_steps_rj
+constexpr int kAccKSteps = 14;             // k_steps_rj: k-steps of J held in AGPRs (the rest in VGPRs)
 constexpr unsigned kSpinLimit = 1u << 22;  // polls before a barrier gives up (seconds)
 constexpr int kHwRegXccId = 20 | (0 << 6) | ((4 - 1) << 11);  // hwreg(HW_REG_XCC_ID, 0, 4)
 
@@ -391,8 +391,10 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
 //
 // Workgroup (g, mb) owns spins [256 mb, 256 mb + 256) of replicas [32 g, 32 g + 32); wave
 // w owns the 64 spins [256 mb + 64 w, +64) and keeps its 64 rows of J, as FP4 (exact for
-// 0 and +-1), in registers for the whole launch (4 row tiles x NKS fragments of 16 bytes
-// per lane: 256 registers at np = 2048).  The four waves read the same Q fragments, which
+// 0 and +-1), in registers for the whole launch: 4 row tiles x NKS fragments of 16 bytes
+// per lane, k-steps [0, kAccKSteps) in accumulation registers (AGPRs, which the MFMA reads
+// directly as its A operand) and the rest in VGPRs; at np = 2048 that is 224 AGPRs of J
+// beside the 16 of the accumulators.  The four waves read the same Q fragments, which
 // come through L1.
 //
 // The 32 replica columns form two independent sub-groups of 16 (column tiles 0 and 1),
@@ -404,15 +406,13 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
 // ---------------------------------------------------------------------------------------
 template <int NKS, bool DISC>
 __global__ void __launch_bounds__(kThreads, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) k_steps_rj(StepArgs a) {
-  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   __shared__ int s_flag;
   __shared__ int s_local;
   constexpr int kPF = kKStepsUnroll;
   static_assert(NKS % kPF == 0 && NKS >= kPF, "k-steps must be a multiple of the prefetch depth");
-  // k-steps [0, NREG) of J live in registers, [NREG, NKS) in LDS (register budget: J,
-  // the state of 2048 elements, the accumulators and the operand prefetch share 512)
-  constexpr int NREG = NKS > kRegKSteps ? kRegKSteps : NKS;
-  constexpr int NLDS = NKS - NREG;
+  // k-steps [0, NACC) of J in AGPRs, [NACC, NKS) in VGPRs
+  constexpr int NACC = NKS > kAccKSteps ? kAccKSteps : NKS;
+  constexpr int NVJ = NKS - NACC;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = blockIdx.x % a.groups;
@@ -426,24 +426,23 @@ __global__ void __launch_bounds__(kThreads, 1) __attribute__((amdgpu_waves_per_e
   unsigned* abort_flag = a.sync + (size_t)(4 * a.groups) * 64;
 
   // J rows of this wave (FP4 fragment-major, 1 KiB per (row tile, k-step)).
-  v4i jr[4][NREG];
-  uint8_t* jl = lds + (size_t)wave * 4 * (NLDS > 0 ? NLDS : 1) * 1024 + lane * 16;  // [rt][ks - NREG][lane]
+  v4i jr[4][NACC];
+  v4i jv[4][NVJ > 0 ? NVJ : 1];
   {
     const uint8_t* jw = static_cast<const uint8_t*>(a.jf) + (size_t)(row0 >> 4) * NKS * 1024 + lane * 16;
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
       for (int ks = 0; ks < NKS; ++ks) {
-        const v4i f = *reinterpret_cast<const v4i*>(jw + (size_t)(rt * NKS + ks) * 1024);
-        if (ks < NREG) jr[rt][ks < NREG ? ks : 0] = f;
-        else *reinterpret_cast<v4i*>(jl + (size_t)(rt * NLDS + (ks - NREG)) * 1024) = f;
+        v4i f = *reinterpret_cast<const v4i*>(jw + (size_t)(rt * NKS + ks) * 1024);
+        if (ks < NACC) {
+          asm volatile("" : "+a"(f));  // place it in AGPRs
+          jr[rt][ks < NACC ? ks : 0] = f;
+        } else {
+          jv[rt][ks < NACC ? 0 : ks - NACC] = f;
+        }
       }
   }
-  v4i jt[2][4];  // LDS part, double-buffered one k-step ahead
-  auto load_jt = [&](int ks, v4i* dst) {
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt) dst[rt] = *reinterpret_cast<const v4i*>(jl + (size_t)(rt * NLDS + (ks - NREG)) * 1024);
-  };
 
   // State: [sub-group = column tile][row tile][v]; lane holds rows 4*(lane/16)+v of column
   // lane%16 of each 16 x 16 tile.
@@ -608,11 +607,10 @@ __global__ void __launch_bounds__(kThreads, 1) __attribute__((amdgpu_waves_per_e
       for (int rt = 0; rt < 4; ++rt) acc[rt] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int ks = 0; ks < NKS; ++ks) {
-        if (ks + 1 >= NREG && ks + 1 < NKS) load_jt(ks + 1, jt[(ks + 1) & 1]);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
-          const v4i f = ks < NREG ? jr[rt][ks < NREG ? ks : 0] : jt[ks & 1][rt];
+          const v4i f = ks < NACC ? jr[rt][ks < NACC ? ks : 0] : jv[rt][ks < NACC ? 0 : ks - NACC];
           acc[rt] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(cat(f, f), bq[ks % kPF], acc[rt], 4, 0, 0,
                                                                      127, 0, 127);
         }
@@ -884,7 +882,8 @@ const void* steps_kernel_for(int form, int kind, int np, bool discrete) {
 size_t steps_lds_bytes(int form, int kind, int np) {
   (void)form;
   const int nks = np / kKS;
-  if (kind == kKindRegJ) return nks > kRegKSteps ? (size_t)4 * 4 * (nks - kRegKSteps) * 1024 : 0;
+  (void)nks;
+  (void)kind;
   return 0;
 }
 
