@@ -222,7 +222,7 @@ gsb_status plan(gsb_ctx* c, int R, int M, Layout* L, int* kind_out) {
   L->Q = take(2 * L->q_buf_bytes);
   L->sync = take(sync_words(chunk_rp / bn) * 4);
   L->status = take(256);
-  L->partial = take(energy_partial_doubles(np, rp) * 8);
+  L->partial = take(std::max(energy_partial_doubles(np, rp) * 8, energy_fp4_scratch_bytes(np, rp)));
   L->E = take((size_t)rp * 8);
   L->best = take(256);
   L->spins = take((size_t)std::max(rp, 1) * c->n_user + 256);
@@ -288,7 +288,12 @@ gsb_status check_status_word(gsb_ctx* c) {
 
 gsb_status compute_energy(gsb_ctx* c) {
   if (c->energy_valid) return GSB_OK;
-  HIP_TRY(launch_energy(c->j32, c->n, c->np, c->rp, c->R, c->X, c->partial, c->E, c->stream), "energy kernel");
+  if (c->pm1 && c->jf_form == kFormFP8 * 2 + 1) {
+    // J in {0, +-1} is on the device as FP4: the exact integer energy runs on MFMA
+    HIP_TRY(launch_energy_fp4(c->jf, c->np, c->rp, c->R, c->X, c->partial, c->E, c->stream), "energy kernel");
+  } else {
+    HIP_TRY(launch_energy(c->j32, c->n, c->np, c->rp, c->R, c->X, c->partial, c->E, c->stream), "energy kernel");
+  }
   c->energy_valid = true;
   return GSB_OK;
 }

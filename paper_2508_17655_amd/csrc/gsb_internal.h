@@ -70,6 +70,12 @@ int choose_kind(int form, int np);
 hipError_t launch_energy(const float* j32, int n, int np, int rp, int r_count, const float* x,
                          double* partial, double* energies, hipStream_t stream);
 size_t energy_partial_doubles(int np, int rp);
+// Exact energies for J in {0, +-1} from the FP4 J of the register-resident FP8 path
+// (np a multiple of 256, rp of 32): E = -1/2 s^T J s on MFMA with integer accumulation.
+// `scratch` holds energy_fp4_scratch_bytes(np, rp) bytes.
+hipError_t launch_energy_fp4(const void* jf4, int np, int rp, int r_count, const float* x, void* scratch,
+                             double* energies, hipStream_t stream);
+size_t energy_fp4_scratch_bytes(int np, int rp);
 hipError_t launch_best(const double* energies, int r_count, int* best_idx, double* best_e,
                        hipStream_t stream);
 hipError_t launch_spins(const float* x, int n_out, int np, int r_first, int r_count, int anc,

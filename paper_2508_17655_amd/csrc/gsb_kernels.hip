@@ -802,6 +802,77 @@ __global__ void k_energy_final(const double* partial, int nyb, int rp, int r_cou
   E[r] = -0.5 * acc;
 }
 
+// Exact energies on MFMA for J in {0, +-1} (eq. (1)): E_r = -1/2 sum_i s_i (J s)_i with
+// s = sgn x.  The spins go into the FP8 operand layout of the step kernels (+-1 exactly),
+// J is the FP4 copy of the register-resident path; every partial sum is an integer of
+// magnitude below 2^24, so the binary32 accumulators are exact, and the per-replica
+// totals are integer atomics, hence independent of order.
+__global__ void k_sign_fp8(const float* x, int np, int nks, int rp, uint8_t* s8) {
+  const size_t quads = (size_t)rp * np / 4;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < quads; t += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)((t * 4) / np), k = (int)((t * 4) % np);
+    const v4f v = *reinterpret_cast<const v4f*>(x + (size_t)r * np + k);
+    unsigned w = 0x38383838u;  // +1.0 in every byte
+    w |= (v[0] < 0.0f ? 0x80u : 0u) | (v[1] < 0.0f ? 0x8000u : 0u) | (v[2] < 0.0f ? 0x800000u : 0u) |
+         (v[3] < 0.0f ? 0x80000000u : 0u);
+    const int kc = k >> 7, kk = k & 127;
+    const int lanep = (r & 15) + 16 * (kk >> 5);
+    const size_t off = ((size_t)((r >> 4) * nks + kc) * 2 + ((kk & 31) >> 4)) * 1024 + lanep * 16 + (kk & 15);
+    *reinterpret_cast<unsigned*>(s8 + off) = w;
+  }
+}
+
+// Workgroup (cg, mb): spins [256 mb, +256) (64 per wave, 4 row tiles) x replicas
+// [32 cg, +32) (2 column tiles).  G = J S over all k-steps, then sum_i s_i G_ir.
+__global__ void __launch_bounds__(256) k_energy_mfma(const uint8_t* jf4, const uint8_t* s8, const float* x, int np,
+                                                     int nks, int* eacc) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cg = blockIdx.x, mb = blockIdx.y;
+  const int row0 = mb * 256 + wave * 64;
+  v4f acc[4][2];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int ks = 0; ks < nks; ++ks) {
+    v4i a[4];
+    v8i b[2];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+      a[rt] = *reinterpret_cast<const v4i*>(jf4 + ((size_t)((row0 >> 4) + rt) * nks + ks) * 1024 + lane * 16);
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const uint8_t* f = s8 + ((size_t)(2 * cg + ct) * nks + ks) * 2048 + lane * 16;
+      b[ct] = cat(*reinterpret_cast<const v4i*>(f), *reinterpret_cast<const v4i*>(f + 1024));
+    }
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+        acc[rt][ct] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(cat(a[rt], a[rt]), b[ct], acc[rt][ct], 4, 0, 0,
+                                                                       127, 0, 127);
+  }
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct) {
+    const int r = 32 * cg + 16 * ct + (lane & 15);
+    float part = 0.0f;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      const v4f xv = *reinterpret_cast<const v4f*>(x + (size_t)r * np + row0 + rt * 16 + 4 * (lane >> 4));
+#pragma unroll
+      for (int v = 0; v < 4; ++v) part += xv[v] < 0.0f ? -acc[rt][ct][v] : acc[rt][ct][v];
+    }
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    if (lane < 16) atomicAdd(eacc + r, (int)part);
+  }
+}
+
+__global__ void k_energy_final_int(const int* eacc, int r_count, double* E) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < r_count) E[r] = -0.5 * (double)eacc[r];
+}
+
 // argmin_r E_r, ties to the lowest r.
 __global__ void __launch_bounds__(256) k_best(const double* E, int r_count, int* best_idx, double* best_e) {
   __shared__ double se[256];
@@ -960,6 +1031,25 @@ hipError_t launch_energy(const float* j32, int n, int np, int rp, int r_count, c
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_energy_final, dim3((r_count + 255) / 256), dim3(256), 0, stream, partial, nyb, rp,
                      r_count, energies);
+  return hipGetLastError();
+}
+
+size_t energy_fp4_scratch_bytes(int np, int rp) { return (size_t)rp * np + (size_t)rp * 4 + 256; }
+
+hipError_t launch_energy_fp4(const void* jf4, int np, int rp, int r_count, const float* x, void* scratch,
+                             double* energies, hipStream_t stream) {
+  if (np % 256 != 0 || rp % 32 != 0) return hipErrorInvalidValue;
+  const int nks = np / kKS;
+  uint8_t* s8 = static_cast<uint8_t*>(scratch);
+  int* eacc = reinterpret_cast<int*>(s8 + (size_t)rp * np);
+  hipError_t e = launch_fill_u32(reinterpret_cast<unsigned*>(eacc), (size_t)rp, 0u, stream);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sign_fp8, dim3(grid_for((size_t)rp * np / 4, 256)), dim3(256), 0, stream, x, np, nks, rp, s8);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_energy_mfma, dim3(rp / 32, np / 256), dim3(256), 0, stream, static_cast<const uint8_t*>(jf4),
+                     s8, x, np, nks, eacc);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_energy_final_int, dim3((r_count + 255) / 256), dim3(256), 0, stream, eacc, r_count, energies);
   return hipGetLastError();
 }
 
