@@ -91,6 +91,13 @@ def _load():
     lib.orc_delta.argtypes = [vp, vp, i32]
     lib.orc_num_threads.restype = i32
     lib.orc_num_threads.argtypes = []
+    lib.orc_init_pairs.restype = None
+    lib.orc_init_pairs.argtypes = [i32, i32, u64, vp, vp]
+    lib.orc_tangent_run_f64.restype = i32
+    lib.orc_tangent_run_f64.argtypes = [vp, i32, i32, i32, dbl, dbl, dbl, i32, i32, i32, i32, i32,
+                                        vp, vp, vp, vp, vp, vp, vp]
+    lib.orc_adjoint_step_f64.restype = i32
+    lib.orc_adjoint_step_f64.argtypes = [vp, i32, i32, dbl, dbl, dbl, dbl, vp, vp, vp, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -227,3 +234,49 @@ def delta(x1: np.ndarray, x2: np.ndarray) -> float:
     x1 = np.ascontiguousarray(x1, dtype=np.float64)
     x2 = np.ascontiguousarray(x2, dtype=np.float64)
     return float(_load().orc_delta(_p(x1), _p(x2), x1.size))
+
+
+def init_pairs(n: int, pairs: int, seed: int):
+    """Trajectory pairs of Sec. IV (replicas 2k, 2k+1): x1 = +-0.1, x2 = x1 +- 2e-6, y = 0.
+    Returns float32 (x, y) of shape (2 pairs, n)."""
+    x = np.empty((2 * pairs, n), dtype=np.float32)
+    y = np.empty((2 * pairs, n), dtype=np.float32)
+    _load().orc_init_pairs(n, pairs, seed, _p(x), _p(y))
+    return x, y
+
+
+def tangent_run(J: np.ndarray, variant: int, *, A: float = 0.0, dt: float, c: float, steps: int,
+                x: np.ndarray, y: np.ndarray, p: np.ndarray | None = None, dx: np.ndarray, dy=None, dp=None,
+                m_begin: int = 0, m_end: int | None = None, schedule: int = SCHED_LINEAR, renorm: int = 1):
+    """Primal and tangent of the continuous-product dynamics in binary64 (bSB, GbSB).
+    Returns (x, y, p, dx, dy, dp, log_growth[replicas]); the tangent comes back with unit norm
+    and log_growth = ln(|v(t_end)| / |v(t_begin)|)."""
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    n = J.shape[0]
+    x = np.array(x, dtype=np.float64, order="C", ndmin=2)
+    R = x.shape[0]
+    y = np.array(y, dtype=np.float64, order="C", ndmin=2)
+    p = np.ones_like(x) if p is None else np.array(p, dtype=np.float64, order="C", ndmin=2)
+    dx = np.array(dx, dtype=np.float64, order="C", ndmin=2)
+    dy = np.zeros_like(x) if dy is None else np.array(dy, dtype=np.float64, order="C", ndmin=2)
+    dp = np.zeros_like(x) if dp is None else np.array(dp, dtype=np.float64, order="C", ndmin=2)
+    lg = np.zeros(R, dtype=np.float64)
+    me = steps if m_end is None else m_end
+    rc = _load().orc_tangent_run_f64(_p(J), n, variant, schedule, A, dt, c, steps, m_begin, me, renorm, R,
+                                     _p(x), _p(y), _p(p), _p(dx), _p(dy), _p(dp), _p(lg))
+    if rc != 0:
+        raise ValueError("oracle tangent run rejected its arguments")
+    return x, y, p, dx, dy, dp, lg
+
+
+def adjoint_step(J: np.ndarray, variant: int, *, A: float, dt: float, c: float, rm: float,
+                 x: np.ndarray, y: np.ndarray, p: np.ndarray, xb: np.ndarray, yb: np.ndarray, pb: np.ndarray):
+    """Cotangents of one step's inputs from those of its outputs, at input state (x, y, p)."""
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    n = J.shape[0]
+    x, y, p = (np.ascontiguousarray(v, dtype=np.float64) for v in (x, y, p))
+    xb, yb, pb = (np.array(v, dtype=np.float64, order="C") for v in (xb, yb, pb))
+    rc = _load().orc_adjoint_step_f64(_p(J), n, variant, A, dt, c, rm, _p(x), _p(y), _p(p), _p(xb), _p(yb), _p(pb))
+    if rc != 0:
+        raise ValueError("oracle adjoint step rejected its arguments")
+    return xb, yb, pb

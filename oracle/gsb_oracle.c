@@ -18,7 +18,10 @@
  *   - PXY arithmetic in 32-bit floating point (Fig. 2(a) caption, App. C).
  *   - initial conditions: x_i(0) uniform in (-0.1, 0.1), y_i(0) = 0 (App. A); the
  *     two-trajectory chaos start x = +-0.1 (Sec. IV).
- *   - normalised distance delta, eq. (8), Sec. IV.
+ *   - normalised distance delta, eq. (8), and its trajectory pairs, Sec. IV.
+ *   - forward and reverse derivatives of one continuous-product step, and the
+ *     largest-Lyapunov-exponent estimate built on the forward one (not in the paper,
+ *     which measures chaos with delta; the derivative is of eqs. (3)-(5), (7)).
  *
  * Two arithmetic modes:
  *   fp64 : every state variable and operation in binary64 (the "truth" used for
@@ -302,6 +305,161 @@ int orc_run_f32(const double* J, int n, int variant, int sched, int form, double
     free(q); free(g);
   }
   return bad ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Chaos diagnostics (Sec. IV) and the derivatives of one step.               */
+/* ------------------------------------------------------------------------- */
+
+/* Trajectory pairs of Sec. IV.  Pair k is replicas 2k and 2k+1:
+ *   x1_i = +-0.1, the sign from bit 63 of the draw for counter (2k) n + i,
+ *   x2_i = x1_i +- 2e-6, the sign from bit 63 of the draw for counter (2k+1) n + i,
+ *   y = 0 for both (draw = SplitMix64 output number counter + 1, as in orc_init_state).
+ * x2 is evaluated in binary64 from the binary32 x1 and rounded to binary32 once.  So x1
+ * of pair k is x of replica k under ORC_INIT_PM01. */
+void orc_init_pairs(int n, int pairs, uint64_t seed, float* x, float* y) {
+  for (int k = 0; k < pairs; ++k) {
+    for (int i = 0; i < n; ++i) {
+      uint64_t c0 = (uint64_t)(2 * (int64_t)k + 0) * (uint64_t)n + (uint64_t)i;
+      uint64_t c1 = (uint64_t)(2 * (int64_t)k + 1) * (uint64_t)n + (uint64_t)i;
+      float x1 = (orc_splitmix64_at(seed, c0 + 1) >> 63) ? -0.1f : 0.1f;
+      double d = (orc_splitmix64_at(seed, c1 + 1) >> 63) ? -2e-6 : 2e-6;
+      x[(size_t)(2 * k) * n + i] = x1;
+      x[(size_t)(2 * k + 1) * n + i] = (float)((double)x1 + d);
+      y[(size_t)(2 * k) * n + i] = 0.0f;
+      y[(size_t)(2 * k + 1) * n + i] = 0.0f;
+    }
+  }
+}
+
+/* Tangent (forward derivative) of the continuous-product step, binary64.  Variants bSB
+ * and GbSB only: the sign product of dSB/GdSB is piecewise constant, its derivative 0.
+ * Differentiating eqs. (7), (3), (4), (5) with f = 1 - A x^2 and r = r_m:
+ *   p' = p (1 - f r)                     dp' = dp (1 - f r) + 2 A x dx p r
+ *   y' = y - p' x dt + c dt (J x)        dy' = dy - (dp' x + p' dx) dt + c dt (J dx)
+ *   x' = x + y' dt                       dx' = dx + dy' dt
+ * and where the wall acts (|x'| > 1: x becomes the constant +-1, y becomes 0) the
+ * component's dx' and dy' are 0.  One replica, steps m_begin .. m_end-1; the tangent
+ * is first scaled to unit norm over (dx, dy, dp), then after every `renorm` steps (and
+ * after the last) ln of its norm is added to *log_growth and it is scaled back to 1,
+ * so *log_growth = ln(|v(t_end)| / |v(t_begin)|) of the unnormalised tangent. */
+static void tangent_replica_f64(const double* J, int n, int sched, double a, double dt, double c, int M,
+                                int m_begin, int m_end, int renorm, double* x, double* y, double* p,
+                                double* dx, double* dy, double* dp, double* g, double* gd,
+                                double* log_growth) {
+  const double cdt = c * dt;
+  double nrm = 0.0;
+  for (int i = 0; i < n; ++i) nrm += dx[i] * dx[i] + dy[i] * dy[i] + dp[i] * dp[i];
+  nrm = sqrt(nrm);
+  for (int i = 0; i < n; ++i) { dx[i] /= nrm; dy[i] /= nrm; dp[i] /= nrm; }
+  double lg = 0.0;
+  for (int m = m_begin; m < m_end; ++m) {
+    const double rm = (sched == ORC_SCHED_LINEAR) ? 1.0 / (double)(M - m) : 0.0;
+    for (int i = 0; i < n; ++i) { /* the two products, J x and J dx, in ascending j */
+      double s = 0.0, sd = 0.0;
+      const double* Ji = J + (size_t)i * n;
+      for (int j = 0; j < n; ++j) { s += Ji[j] * x[j]; sd += Ji[j] * dx[j]; }
+      g[i] = s; gd[i] = sd;
+    }
+    for (int i = 0; i < n; ++i) {
+      const double xi = x[i], yi = y[i], pi = p[i];
+      const double f = 1.0 - a * (xi * xi);
+      const double pn = pi - (f * pi) * rm;
+      const double yn = (yi + (-(pn * xi) * dt)) + cdt * g[i];
+      const double xn = xi + yn * dt;
+      const double dpn = dp[i] * (1.0 - f * rm) + 2.0 * a * xi * dx[i] * pi * rm;
+      const double dyn = dy[i] - (dpn * xi + pn * dx[i]) * dt + cdt * gd[i];
+      const double dxn = dx[i] + dyn * dt;
+      if (fabs(xn) > 1.0) {
+        x[i] = xn > 0 ? 1.0 : -1.0; y[i] = 0.0; dx[i] = 0.0; dy[i] = 0.0;
+      } else {
+        x[i] = xn; y[i] = yn; dx[i] = dxn; dy[i] = dyn;
+      }
+      p[i] = pn; dp[i] = dpn;
+    }
+    const int done = m + 1 - m_begin;
+    if ((renorm > 0 && done % renorm == 0) || m + 1 == m_end) {
+      double s = 0.0;
+      for (int i = 0; i < n; ++i) s += dx[i] * dx[i] + dy[i] * dy[i] + dp[i] * dp[i];
+      s = sqrt(s);
+      lg += log(s);
+      for (int i = 0; i < n; ++i) { dx[i] /= s; dy[i] /= s; dp[i] /= s; }
+    }
+  }
+  *log_growth = lg;
+}
+
+/* Batch of replicas, arrays [replicas][n]; log_growth [replicas].  The largest
+ * Lyapunov exponent estimate over the interval is log_growth / ((m_end - m_begin) dt).
+ * Returns 0, or -1 on bad arguments (also for the sign-product variants). */
+int orc_tangent_run_f64(const double* J, int n, int variant, int sched, double A, double dt, double c, int M,
+                        int m_begin, int m_end, int renorm, int replicas, double* x, double* y, double* p,
+                        double* dx, double* dy, double* dp, double* log_growth) {
+  if (n <= 0 || replicas <= 0 || M <= 0 || m_begin < 0 || m_end > M || m_begin > m_end) return -1;
+  if (is_discrete(variant)) return -1;
+  const double a = has_control(variant) ? A : 0.0;
+  int bad = 0;
+#pragma omp parallel for schedule(static)
+  for (int r = 0; r < replicas; ++r) {
+    double* g = (double*)malloc(sizeof(double) * (size_t)n);
+    double* gd = (double*)malloc(sizeof(double) * (size_t)n);
+    if (!g || !gd) { bad = 1; free(g); free(gd); continue; }
+    size_t o = (size_t)r * n;
+    tangent_replica_f64(J, n, sched, a, dt, c, M, m_begin, m_end, renorm, x + o, y + o, p + o, dx + o, dy + o,
+                        dp + o, g, gd, log_growth + r);
+    free(g); free(gd);
+  }
+  return bad ? -1 : 0;
+}
+
+/* Adjoint (reverse derivative) of one continuous-product step, binary64, for one
+ * replica at the step's input state (x, y, p) and r = r_m.  On entry (xb, yb, pb) are
+ * the cotangents of the step's outputs; on return, of its inputs.  Transposing the
+ * tangent above (J symmetric, so J^T w = J w) with k_i = [|x'_i| > 1]:
+ *   w   = (1 - k) (yb + dt xb)
+ *   pb' = pb - dt x w
+ *   xb  = (1 - k) xb - dt p' w + c dt (J w) + 2 A x p r pb'
+ *   yb  = w,  pb = pb' (1 - f r). */
+int orc_adjoint_step_f64(const double* J, int n, int variant, double A, double dt, double c, double rm,
+                         const double* x, const double* y, const double* p, double* xb, double* yb, double* pb) {
+  if (n <= 0 || is_discrete(variant)) return -1;
+  const double a = has_control(variant) ? A : 0.0;
+  const double cdt = c * dt;
+  double* g = (double*)malloc(sizeof(double) * (size_t)n);
+  double* w = (double*)malloc(sizeof(double) * (size_t)n);
+  double* gw = (double*)malloc(sizeof(double) * (size_t)n);
+  if (!g || !w || !gw) { free(g); free(w); free(gw); return -1; }
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    const double* Ji = J + (size_t)i * n;
+    for (int j = 0; j < n; ++j) s += Ji[j] * x[j];
+    g[i] = s;
+  }
+  for (int i = 0; i < n; ++i) { /* forward step again, for p' and the wall mask */
+    const double f = 1.0 - a * (x[i] * x[i]);
+    const double pn = p[i] - (f * p[i]) * rm;
+    const double yn = (y[i] + (-(pn * x[i]) * dt)) + cdt * g[i];
+    const double xn = x[i] + yn * dt;
+    const int k = fabs(xn) > 1.0;
+    w[i] = k ? 0.0 : (yb[i] + dt * xb[i]);
+    if (k) xb[i] = 0.0;
+  }
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    const double* Ji = J + (size_t)i * n;
+    for (int j = 0; j < n; ++j) s += Ji[j] * w[j];
+    gw[i] = s;
+  }
+  for (int i = 0; i < n; ++i) {
+    const double f = 1.0 - a * (x[i] * x[i]);
+    const double pn = p[i] - (f * p[i]) * rm;
+    const double pbn = pb[i] - dt * x[i] * w[i];
+    xb[i] = xb[i] - dt * pn * w[i] + cdt * gw[i] + 2.0 * a * x[i] * p[i] * rm * pbn;
+    yb[i] = w[i];
+    pb[i] = pbn * (1.0 - f * rm);
+  }
+  free(g); free(w); free(gw);
+  return 0;
 }
 
 /* ------------------------------------------------------------------------- */
