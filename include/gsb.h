@@ -73,8 +73,11 @@ typedef enum { GSB_PREC_FP32 = 0, GSB_PREC_BF16X2 = 1, GSB_PREC_FP8 = 2 } gsb_pr
  * depend on the replica count).
  *   X    : x ~ U(-0.1, 0.1), y = 0 (App. A; default).
  *   XY   : x and y ~ U(-0.1, 0.1).
- *   PM01 : x = +-0.1 with a random sign, y = 0 (the chaos start of Sec. IV). */
-typedef enum { GSB_INIT_X = 0, GSB_INIT_XY = 1, GSB_INIT_PM01 = 2 } gsb_init_mode;
+ *   PM01 : x = +-0.1 with a random sign, y = 0 (the chaos start of Sec. IV).
+ *   PAIRS: the trajectory pairs of Sec. IV: replica 2k starts at x = +-0.1 (replica k's
+ *          PM01 start), replica 2k+1 at the same x +- 2e-6 (independent random signs,
+ *          binary64 sum rounded to binary32 once), y = 0 for both; delta(0) = 1e-6. */
+typedef enum { GSB_INIT_X = 0, GSB_INIT_XY = 1, GSB_INIT_PM01 = 2, GSB_INIT_PAIRS = 3 } gsb_init_mode;
 
 /* Options for gsb_set / gsb_get. */
 typedef enum {
@@ -171,6 +174,44 @@ gsb_status gsb_state(gsb_ctx* ctx, float* x, float* y, float* p, int32_t* m);
  * gsb_state, all non-NULL and finite, |x| <= 1; 0 <= m <= M.  Synchronises.
  * Errors: ESTATE, EINVAL, ENONFINITE, EDEVICE. */
 gsb_status gsb_set_state(gsb_ctx* ctx, const float* x, const float* y, const float* p, int32_t m);
+
+/* Normalised distance of the trajectory pairs, eq. (8) (Sec. IV), at the current step:
+ * delta_k = sqrt(sum_i (x_i(2k) - x_i(2k+1))^2 / (4 n)) over the n spins of the instance
+ * (a field ancilla excluded), for k < replicas/2.  Meaningful for runs started with
+ * GSB_INIT_PAIRS.  out: host, replicas/2 doubles (binary64).  Synchronises.
+ * Errors: ESTATE (no run), EINVAL (NULL, fewer than 2 replicas), EDEVICE. */
+gsb_status gsb_delta(gsb_ctx* ctx, double* out);
+
+/* Largest-Lyapunov-exponent estimates (a chaos measure beside eq. (8); not in the paper).
+ * Runs `replicas` replicas of bSB or GbSB (continuous product; the sign product's
+ * derivative is 0) for M = `steps` steps in the binary32 (FP32) form, each with the
+ * forward derivative of every step (of eqs. (7), (3), (4), (5): dp' = dp (1 - f r_m) +
+ * 2 A x dx p r_m with f = 1 - A x^2; dy' = dy - (dp' x + p' dx) dt + c dt (J dx);
+ * dx' = dx + dy' dt; dx' = dy' = 0 where the wall acts).  The J dx products share the
+ * GEMM of the J x products (2 replicas' worth of columns per replica).
+ *   variant          : GSB_BSB or GSB_GBSB.     schedule, dt, seed: as gsb_init; the
+ *                      primal start of replica r equals gsb_init's for the same seed and
+ *                      GSB_OPT_INIT_MODE.
+ *   control_strength : A for every replica when A_per_replica is NULL.
+ *   A_per_replica    : host, `replicas` doubles >= 0, or NULL (a sweep over A in one run).
+ *   tangent_seed     : starting tangent dx_i = +-1 (bit 63 of SplitMix64 output
+ *                      r*n_dyn + i + 1 of tangent_seed), dy = dp = 0, scaled to unit norm
+ *                      over (dx, dy, dp).
+ *   renorm_every     : steps between rescalings of the tangent to unit norm (>= 1); the
+ *                      logarithms of the norms are summed in binary64.
+ *   lle              : host, `replicas` doubles: ln(|v(t_M)| / |v(0)|) / (M dt), or -inf
+ *                      when every component of the tangent reached a wall.
+ *   state_out        : host, 6 * replicas * n_dyn floats or NULL: x, y, p, dx, dy, dp at
+ *                      t_M (the tangent at unit norm), each replica-major.
+ * Uses the context's workspace; afterwards the context has no current run (ESTATE for
+ * gsb_step, gsb_energy, ...).  gsb_last_step_ms reports its device time.  Synchronises.
+ * Errors: EINVAL, ENOMEM, EUNSUPPORTED, EDEVICE. */
+/* Device memory gsb_lle needs for `replicas` replicas and `steps` steps, in bytes. */
+gsb_status gsb_lle_workspace_size(gsb_ctx* ctx, int32_t replicas, int32_t steps, size_t* bytes);
+
+gsb_status gsb_lle(gsb_ctx* ctx, int32_t variant, int32_t schedule, double control_strength,
+                   const double* A_per_replica, double dt, int32_t replicas, int32_t steps, uint64_t seed,
+                   uint64_t tangent_seed, int32_t renorm_every, double* lle, float* state_out);
 
 /* Device time of the last gsb_step/gsb_run time stepping (the persistent step kernel
  * launches), in milliseconds, measured with HIP events on the context's stream.

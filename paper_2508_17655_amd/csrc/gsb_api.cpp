@@ -188,26 +188,31 @@ namespace {
 
 struct Layout {
   size_t j32, jf, rtab, X, Y, P, Q, sync, status, partial, E, best, spins, total;
+  size_t acol = 0, lg = 0, ext = 0;  // tangent mode only
   size_t q_buf_bytes;
-  int chunk_rp;
+  int chunk_rp;  // columns per launch
 };
 
-gsb_status plan(gsb_ctx* c, int R, int M, Layout* L, int* kind_out) {
-  const int form = form_of(c->precision);
+// Workspace of a run of R replicas over M steps.  Tangent mode (gsb_lle): binary32 form,
+// generic kernel, two columns per replica (replica + tangent), plus the per-replica
+// control strengths, log-norm sums and the extraction buffer.
+gsb_status plan(gsb_ctx* c, int R, int M, Layout* L, int* kind_out, bool tangent = false) {
+  const int form = tangent ? (int)kFormFP32 : form_of(c->precision);
   const int np = c->np;
   const int rp = (R + kRepPad - 1) / kRepPad * kRepPad;
-  const int kind = choose_kind(form, np);
+  const int cols = tangent ? 2 * rp : rp;
+  const int kind = tangent ? (int)kKindGeneric : choose_kind(form, np);
   const int bm = tile_rows_kind(kind), bn = tile_cols_kind(kind);
   int dev_count = 0;
   if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1)
     return fail(GSB_EDEVICE, "no HIP device");
-  const int max_wg = max_coresident_workgroups(form, kind, np);
+  const int max_wg = max_coresident_workgroups(form, kind, np, tangent);
   if (max_wg < 1) return fail(GSB_EDEVICE, "occupancy query failed for the step kernel");
   const int nb = np / bm;
   const int max_groups = max_wg / nb;
   if (max_groups < 1)
     return fail(GSB_EUNSUPPORTED, "n too large for one co-resident replica group on this device");
-  const int chunk_rp = std::min(rp, max_groups * bn / kRepPad * kRepPad);
+  const int chunk_rp = std::min(cols, max_groups * bn / kRepPad * kRepPad);
   if (chunk_rp < kRepPad)
     return fail(GSB_EUNSUPPORTED, "n too large for one co-resident replica block on this device");
   size_t off = 0;
@@ -215,9 +220,9 @@ gsb_status plan(gsb_ctx* c, int R, int M, Layout* L, int* kind_out) {
   L->j32 = take((size_t)np * np * 4);
   L->jf = take((size_t)np * np * operand_elem_bytes(form));  // FP4 J uses half of it
   L->rtab = take((size_t)M * 4);
-  L->X = take((size_t)rp * np * 4);
-  L->Y = take((size_t)rp * np * 4);
-  L->P = take((size_t)rp * np * 4);
+  L->X = take((size_t)cols * np * 4);
+  L->Y = take((size_t)cols * np * 4);
+  L->P = take((size_t)cols * np * 4);
   L->q_buf_bytes = (size_t)chunk_rp * np * operand_elem_bytes(form) * operand_planes(form);
   L->Q = take(2 * L->q_buf_bytes);
   L->sync = take(sync_words(chunk_rp / bn) * 4);
@@ -226,6 +231,11 @@ gsb_status plan(gsb_ctx* c, int R, int M, Layout* L, int* kind_out) {
   L->E = take((size_t)rp * 8);
   L->best = take(256);
   L->spins = take((size_t)std::max(rp, 1) * c->n_user + 256);
+  if (tangent) {
+    L->acol = take((size_t)rp * 4);
+    L->lg = take((size_t)rp * 8);
+    L->ext = take((size_t)6 * R * c->n * 4);
+  }
   L->total = off;
   L->chunk_rp = chunk_rp;
   *kind_out = kind;
@@ -386,7 +396,7 @@ gsb_status gsb_set(gsb_ctx* c, int32_t option, double v) {
     }
     case GSB_OPT_INIT_MODE: {
       const int mm = (int)v;
-      if ((double)mm != v || mm < GSB_INIT_X || mm > GSB_INIT_PM01) return fail(GSB_EINVAL, "unknown init mode");
+      if ((double)mm != v || mm < GSB_INIT_X || mm > GSB_INIT_PAIRS) return fail(GSB_EINVAL, "unknown init mode");
       c->init_mode = mm;
       return GSB_OK;
     }
@@ -458,6 +468,92 @@ gsb_status gsb_bind_workspace(gsb_ctx* c, void* ptr, size_t bytes) {
   return GSB_OK;
 }
 
+namespace {
+
+// Point the context's buffers into the workspace laid out by `L`, upload and encode J
+// for product form `form` if the workspace does not hold it yet, and write the schedule
+// table r_m = 1 / (M - m) (eqs. (6), (7)), binary64 rounded once.
+gsb_status carve_and_prepare(gsb_ctx* c, const Layout& L, int kind, int form, int schedule, int steps) {
+  uint8_t* b = c->ws;
+  const bool j32_moved = reinterpret_cast<float*>(b + L.j32) != c->j32;
+  c->j32 = reinterpret_cast<float*>(b + L.j32);
+  if (reinterpret_cast<uint8_t*>(b + L.jf) != c->jf) c->jf_form = -1;
+  c->jf = b + L.jf;
+  if (j32_moved) { c->j32_ready = false; c->jf_form = -1; }
+  c->rtab = reinterpret_cast<float*>(b + L.rtab);
+  c->X = reinterpret_cast<float*>(b + L.X);
+  c->Y = reinterpret_cast<float*>(b + L.Y);
+  c->P = reinterpret_cast<float*>(b + L.P);
+  c->Q = b + L.Q;
+  c->q_buf_bytes = L.q_buf_bytes;
+  c->sync = reinterpret_cast<unsigned*>(b + L.sync);
+  c->status = reinterpret_cast<unsigned*>(b + L.status);
+  c->partial = reinterpret_cast<double*>(b + L.partial);
+  c->E = reinterpret_cast<double*>(b + L.E);
+  c->best_idx = reinterpret_cast<int*>(b + L.best);
+  c->best_e = reinterpret_cast<double*>(b + L.best + 8);
+  c->spins = reinterpret_cast<int8_t*>(b + L.spins);
+  c->chunk_rp = L.chunk_rp;
+  c->kind = kind;
+  if (!c->j32_ready) {
+    HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(c->j32), (size_t)c->np * c->np, 0u, c->stream), "clear J");
+    HIP_TRY(hipMemcpy2DAsync(c->j32, (size_t)c->np * 4, c->J.data(), (size_t)c->n * 4, (size_t)c->n * 4, c->n,
+                             hipMemcpyHostToDevice, c->stream),
+            "upload J");
+    c->j32_ready = true;
+    c->jf_form = -1;
+  }
+  const bool j_fp4 = kind != kKindGeneric;  // the FP8 kinds with J on chip keep J as FP4
+  const int jcode = form * 2 + (j_fp4 ? 1 : 0);
+  if (c->jf_form != jcode) {
+    HIP_TRY(launch_encode_j(form, j_fp4, c->j32, c->np, c->jf, c->stream), "encode J");
+    c->jf_form = jcode;
+  }
+  c->rtab_host.assign(steps, 0.0f);
+  if (schedule == GSB_SCHED_LINEAR)
+    for (int m = 0; m < steps; ++m) c->rtab_host[m] = (float)(1.0 / (double)(steps - m));
+  HIP_TRY(hipMemcpyAsync(c->rtab, c->rtab_host.data(), (size_t)steps * 4, hipMemcpyHostToDevice, c->stream),
+          "upload schedule");
+  HIP_TRY(launch_fill_u32(c->status, 64, 0u, c->stream), "clear status");
+  return GSB_OK;
+}
+
+// Persistent step launches for steps [m0, m1) over `cols` columns of the current
+// buffers, in chunks of c->chunk_rp columns.
+gsb_status launch_chunks(gsb_ctx* c, int form, int cols, bool discrete, float A, const float* acol, int m0, int m1,
+                         bool tangent) {
+  for (int r0 = 0; r0 < cols; r0 += c->chunk_rp) {
+    const int rcount = std::min(c->chunk_rp, cols - r0);
+    StepArgs a;
+    a.n = c->n;
+    a.np = c->np;
+    a.rp = rcount;
+    a.groups = rcount / tile_cols_kind(c->kind);
+    a.nb = c->np / tile_rows_kind(c->kind);
+    a.discrete = discrete ? 1 : 0;
+    a.m_begin = m0;
+    a.m_end = m1;
+    a.A = A;
+    a.dt = (float)c->dt;
+    a.cdt = (float)(c->c * c->dt);
+    a.acol = acol ? acol + r0 / 2 : nullptr;  // tangent mode: 2 columns per replica
+    a.rtab = c->rtab;
+    a.jf = c->jf;
+    a.q = c->Q;
+    a.q_buf_bytes = (size_t)rcount * c->np * operand_elem_bytes(form) * operand_planes(form);
+    a.x = c->X + (size_t)r0 * c->np;
+    a.y = c->Y + (size_t)r0 * c->np;
+    a.p = c->P + (size_t)r0 * c->np;
+    a.sync = c->sync;
+    a.status = c->status;
+    HIP_TRY(launch_fill_u32(c->sync, sync_words(a.groups), 0u, c->stream), "clear sync");
+    HIP_TRY(launch_steps(form, c->kind, a, c->stream, tangent), "step kernel launch");
+  }
+  return GSB_OK;
+}
+
+}  // namespace
+
 gsb_status gsb_init(gsb_ctx* c, int32_t variant, int32_t schedule, double A, double dt, int32_t replicas,
                     int32_t steps, uint64_t seed) {
   g_err.clear();
@@ -481,50 +577,8 @@ gsb_status gsb_init(gsb_ctx* c, int32_t variant, int32_t schedule, double A, dou
   if (s != GSB_OK) return s;
   const int form = form_of(c->precision);
   const int rp = (replicas + kRepPad - 1) / kRepPad * kRepPad;
-  // carve
-  uint8_t* b = c->ws;
-  const bool j32_moved = reinterpret_cast<float*>(b + L.j32) != c->j32;
-  c->j32 = reinterpret_cast<float*>(b + L.j32);
-  if (reinterpret_cast<uint8_t*>(b + L.jf) != c->jf) c->jf_form = -1;
-  c->jf = b + L.jf;
-  if (j32_moved) { c->j32_ready = false; c->jf_form = -1; }
-  c->rtab = reinterpret_cast<float*>(b + L.rtab);
-  c->X = reinterpret_cast<float*>(b + L.X);
-  c->Y = reinterpret_cast<float*>(b + L.Y);
-  c->P = reinterpret_cast<float*>(b + L.P);
-  c->Q = b + L.Q;
-  c->q_buf_bytes = L.q_buf_bytes;
-  c->sync = reinterpret_cast<unsigned*>(b + L.sync);
-  c->status = reinterpret_cast<unsigned*>(b + L.status);
-  c->partial = reinterpret_cast<double*>(b + L.partial);
-  c->E = reinterpret_cast<double*>(b + L.E);
-  c->best_idx = reinterpret_cast<int*>(b + L.best);
-  c->best_e = reinterpret_cast<double*>(b + L.best + 8);
-  c->spins = reinterpret_cast<int8_t*>(b + L.spins);
-  c->chunk_rp = L.chunk_rp;
-  c->kind = kind;
-  // instance upload and encode
-  if (!c->j32_ready) {
-    HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(c->j32), (size_t)c->np * c->np, 0u, c->stream), "clear J");
-    HIP_TRY(hipMemcpy2DAsync(c->j32, (size_t)c->np * 4, c->J.data(), (size_t)c->n * 4, (size_t)c->n * 4, c->n,
-                             hipMemcpyHostToDevice, c->stream),
-            "upload J");
-    c->j32_ready = true;
-    c->jf_form = -1;
-  }
-  const bool j_fp4 = kind != kKindGeneric;  // the FP8 kinds with J on chip keep J as FP4
-  const int jcode = form * 2 + (j_fp4 ? 1 : 0);
-  if (c->jf_form != jcode) {
-    HIP_TRY(launch_encode_j(form, j_fp4, c->j32, c->np, c->jf, c->stream), "encode J");
-    c->jf_form = jcode;
-  }
-  // schedule table r_m = 1 / (M - m) (eqs. (6), (7)), binary64 rounded once
-  c->rtab_host.assign(steps, 0.0f);
-  if (schedule == GSB_SCHED_LINEAR)
-    for (int m = 0; m < steps; ++m) c->rtab_host[m] = (float)(1.0 / (double)(steps - m));
-  HIP_TRY(hipMemcpyAsync(c->rtab, c->rtab_host.data(), (size_t)steps * 4, hipMemcpyHostToDevice, c->stream),
-          "upload schedule");
-  HIP_TRY(launch_fill_u32(c->status, 64, 0u, c->stream), "clear status");
+  s = carve_and_prepare(c, L, kind, form, schedule, steps);
+  if (s != GSB_OK) return s;
   HIP_TRY(launch_init_state(c->n, c->np, rp, seed, c->init_mode, c->X, c->Y, c->P, c->stream), "init state");
   // make the pageable host sources safe to reuse
   HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronise");
@@ -555,32 +609,9 @@ gsb_status gsb_step(gsb_ctx* c, int32_t count) {
     HIP_TRY(hipEventCreate(&c->ev1), "event create");
   }
   HIP_TRY(hipEventRecord(c->ev0, c->stream), "event record");
-  for (int r0 = 0; r0 < c->rp; r0 += c->chunk_rp) {
-    const int rcount = std::min(c->chunk_rp, c->rp - r0);
-    StepArgs a;
-    a.n = c->n;
-    a.np = c->np;
-    a.rp = rcount;
-    a.groups = rcount / tile_cols_kind(c->kind);
-    a.nb = c->np / tile_rows_kind(c->kind);
-    a.discrete = (c->variant == GSB_DSB || c->variant == GSB_GDSB) ? 1 : 0;
-    a.m_begin = c->m;
-    a.m_end = c->m + count;
-    a.A = (float)c->A;
-    a.dt = (float)c->dt;
-    a.cdt = (float)(c->c * c->dt);
-    a.rtab = c->rtab;
-    a.jf = c->jf;
-    a.q = c->Q;
-    a.q_buf_bytes = (size_t)rcount * c->np * operand_elem_bytes(form) * operand_planes(form);
-    a.x = c->X + (size_t)r0 * c->np;
-    a.y = c->Y + (size_t)r0 * c->np;
-    a.p = c->P + (size_t)r0 * c->np;
-    a.sync = c->sync;
-    a.status = c->status;
-    HIP_TRY(launch_fill_u32(c->sync, sync_words(a.groups), 0u, c->stream), "clear sync");
-    HIP_TRY(launch_steps(form, c->kind, a, c->stream), "step kernel launch");
-  }
+  gsb_status st = launch_chunks(c, form, c->rp, c->variant == GSB_DSB || c->variant == GSB_GDSB, (float)c->A,
+                                nullptr, c->m, c->m + count, false);
+  if (st != GSB_OK) return st;
   HIP_TRY(hipEventRecord(c->ev1, c->stream), "event record");
   c->timed = true;
   c->m += count;
@@ -677,6 +708,103 @@ gsb_status gsb_set_state(gsb_ctx* c, const float* x, const float* y, const float
   HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronise");
   c->m = m;
   c->energy_valid = false;
+  return GSB_OK;
+}
+
+gsb_status gsb_delta(gsb_ctx* c, double* out) {
+  g_err.clear();
+  if (!c || !out) return fail(GSB_EINVAL, "NULL argument");
+  if (!c->inited) return fail(GSB_ESTATE, "no run");
+  if (c->R < 2) return fail(GSB_EINVAL, "delta needs at least one pair of replicas");
+  const int pairs = c->R / 2;
+  HIP_TRY(launch_delta(c->n_user, c->np, pairs, c->X, c->partial, c->stream), "delta kernel");
+  HIP_TRY(hipMemcpyAsync(out, c->partial, (size_t)pairs * 8, hipMemcpyDeviceToHost, c->stream), "copy delta");
+  return check_status_word(c);
+}
+
+gsb_status gsb_lle_workspace_size(gsb_ctx* c, int32_t replicas, int32_t steps, size_t* bytes) {
+  g_err.clear();
+  if (!c || !bytes) return fail(GSB_EINVAL, "NULL argument");
+  if (replicas < 1 || steps < 1) return fail(GSB_EINVAL, "replicas and steps must be >= 1");
+  Layout L;
+  int kind;
+  gsb_status s = plan(c, replicas, steps, &L, &kind, true);
+  if (s != GSB_OK) return s;
+  *bytes = L.total;
+  return GSB_OK;
+}
+
+gsb_status gsb_lle(gsb_ctx* c, int32_t variant, int32_t schedule, double A, const double* A_per_replica, double dt,
+                   int32_t replicas, int32_t steps, uint64_t seed, uint64_t tangent_seed, int32_t renorm_every,
+                   double* lle, float* state_out) {
+  g_err.clear();
+  if (!c || !lle) return fail(GSB_EINVAL, "NULL argument");
+  if (variant != GSB_BSB && variant != GSB_GBSB)
+    return fail(GSB_EINVAL, "the tangent needs a continuous product: variant must be GSB_BSB or GSB_GBSB");
+  if (schedule < GSB_SCHED_LINEAR || schedule > GSB_SCHED_CONSTANT) return fail(GSB_EINVAL, "unknown schedule");
+  if (!std::isfinite(dt) || dt <= 0) return fail(GSB_EINVAL, "dt must be finite and > 0");
+  if (replicas < 1 || replicas > (1 << 20)) return fail(GSB_EINVAL, "replicas must be in [1, 2^20]");
+  if (steps < 1 || steps > (1 << 24)) return fail(GSB_EINVAL, "steps must be in [1, 2^24]");
+  if (renorm_every < 1) return fail(GSB_EINVAL, "renorm_every must be >= 1");
+  std::vector<float> acol_host;
+  try {
+    acol_host.assign((size_t)(replicas + kRepPad - 1) / kRepPad * kRepPad, 0.0f);
+  } catch (...) {
+    return fail(GSB_ENOMEM, "host allocation failed");
+  }
+  for (int r = 0; r < replicas; ++r) {
+    const double a = A_per_replica ? A_per_replica[r] : A;
+    if (!std::isfinite(a) || a < 0) return fail(GSB_EINVAL, "control strengths must be finite and >= 0");
+    acol_host[r] = variant == GSB_GBSB ? (float)a : 0.0f;
+  }
+  if (!c->c_set) {
+    ensure_eig(c);
+    c->c = c->lmax > 0 ? 1.0 / c->lmax : 1.0;  // App. A: c = 1 / lambda_max
+  }
+  Layout L;
+  int kind;
+  gsb_status s = plan(c, replicas, steps, &L, &kind, true);
+  if (s != GSB_OK) return s;
+  s = ensure_workspace(c, L.total);
+  if (s != GSB_OK) return s;
+  c->inited = false;  // the workspace now holds the tangent-mode layout
+  c->energy_valid = false;
+  c->timed = false;
+  const int rp = (int)acol_host.size();
+  s = carve_and_prepare(c, L, kind, kFormFP32, schedule, steps);
+  if (s != GSB_OK) return s;
+  float* acol = reinterpret_cast<float*>(c->ws + L.acol);
+  double* lg = reinterpret_cast<double*>(c->ws + L.lg);
+  float* ext = reinterpret_cast<float*>(c->ws + L.ext);
+  c->dt = dt;
+  HIP_TRY(hipMemcpyAsync(acol, acol_host.data(), (size_t)rp * 4, hipMemcpyHostToDevice, c->stream), "upload A");
+  HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(lg), (size_t)rp * 2, 0u, c->stream), "clear log sums");
+  HIP_TRY(launch_init_tangent(c->n, c->np, rp, seed, c->init_mode, tangent_seed, c->X, c->Y, c->P, c->stream),
+          "init state and tangent");
+  HIP_TRY(launch_tangent_renorm(c->n, c->np, rp, c->X, c->Y, c->P, lg, false, c->stream), "normalise tangent");
+  if (!c->ev0) {
+    HIP_TRY(hipEventCreate(&c->ev0), "event create");
+    HIP_TRY(hipEventCreate(&c->ev1), "event create");
+  }
+  HIP_TRY(hipEventRecord(c->ev0, c->stream), "event record");
+  for (int m0 = 0; m0 < steps; m0 += renorm_every) {
+    const int m1 = std::min(steps, m0 + renorm_every);
+    s = launch_chunks(c, kFormFP32, 2 * rp, false, 0.0f, acol, m0, m1, true);
+    if (s != GSB_OK) return s;
+    HIP_TRY(launch_tangent_renorm(c->n, c->np, rp, c->X, c->Y, c->P, lg, true, c->stream), "renormalise tangent");
+  }
+  HIP_TRY(hipEventRecord(c->ev1, c->stream), "event record");
+  c->timed = true;
+  std::vector<double> lg_host((size_t)replicas);
+  HIP_TRY(hipMemcpyAsync(lg_host.data(), lg, (size_t)replicas * 8, hipMemcpyDeviceToHost, c->stream), "copy logs");
+  if (state_out) {
+    HIP_TRY(launch_tangent_extract(c->n, c->np, replicas, c->X, c->Y, c->P, ext, c->stream), "extract state");
+    HIP_TRY(hipMemcpyAsync(state_out, ext, (size_t)6 * replicas * c->n * 4, hipMemcpyDeviceToHost, c->stream),
+            "copy state");
+  }
+  s = check_status_word(c);
+  if (s != GSB_OK) return s;
+  for (int r = 0; r < replicas; ++r) lle[r] = lg_host[r] / ((double)steps * dt);
   return GSB_OK;
 }
 

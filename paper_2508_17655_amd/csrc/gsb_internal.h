@@ -47,6 +47,7 @@ struct StepArgs {
   int discrete;   // 1: operand is sgn(x) (dSB, GdSB)
   int m_begin, m_end;
   float A, dt, cdt;
+  const float* acol;      // per-replica control strength (tangent mode), or nullptr
   const float* rtab;      // r_m, m = 0..M-1
   const void* jf;         // J in the fragment-major layout of `form`
   uint8_t* q;             // operand ping-pong buffers of this launch
@@ -63,9 +64,23 @@ hipError_t launch_fill_u32(unsigned* p, size_t count, unsigned v, hipStream_t st
 hipError_t launch_encode_j(int form, bool fp4, const float* j32, int np, void* jf, hipStream_t stream);
 hipError_t launch_init_state(int n, int np, int rp, uint64_t seed, int mode, float* x, float* y,
                              float* p, hipStream_t stream);
-// Persistent step kernel of variant `kind` (see Kind).
-hipError_t launch_steps(int form, int kind, const StepArgs& a, hipStream_t stream);
-int max_coresident_workgroups(int form, int kind, int np);
+// Persistent step kernel of variant `kind` (see Kind).  With `tangent` (binary32 form,
+// generic kind, continuous variants) the launch's columns are the tangent-mode layout:
+// blocks of 32 = 16 replicas followed by their 16 tangents.
+hipError_t launch_steps(int form, int kind, const StepArgs& a, hipStream_t stream, bool tangent = false);
+int max_coresident_workgroups(int form, int kind, int np, bool tangent = false);
+// Tangent mode: starting state (as launch_init_state for each replica) and tangent
+// dx = +-1 from `tseed` (dy = dp = 0) for rp replicas in 2 rp columns.
+hipError_t launch_init_tangent(int n, int np, int rp, uint64_t seed, int mode, uint64_t tseed, float* x, float* y,
+                               float* p, hipStream_t stream);
+// Scale every replica's tangent to unit norm; with `accumulate`, lg[r] += ln(norm).
+hipError_t launch_tangent_renorm(int n, int np, int rp, float* x, float* y, float* p, double* lg, bool accumulate,
+                                 hipStream_t stream);
+// Tangent-mode state of the first R replicas -> [6][R][n] (x, y, p, dx, dy, dp).
+hipError_t launch_tangent_extract(int n, int np, int R, const float* x, const float* y, const float* p, float* out,
+                                  hipStream_t stream);
+// eq. (8) for pairs (2k, 2k + 1), k < pairs, over spins < n.
+hipError_t launch_delta(int n, int np, int pairs, const float* x, double* out, hipStream_t stream);
 int choose_kind(int form, int np);
 hipError_t launch_energy(const float* j32, int n, int np, int rp, int r_count, const float* x,
                          double* partial, double* energies, hipStream_t stream);

@@ -146,9 +146,17 @@ __device__ __forceinline__ void store_operand(uint8_t* qbuf, size_t plane_bytes,
 // keeps x, y, p of those 2048 elements in registers for the whole launch.  Workgroup b
 // is (g, mb) = (b mod groups, b div groups): with 8 or 16 groups, round-robin dispatch
 // puts each group on one XCD.
+//
+// TANG (binary32 product, continuous variants): the launch's columns come in blocks of
+// 32 whose first 16 are replicas and whose last 16 carry the forward derivative (the
+// tangent) of the same 16 replicas, so one lane holds an element's state and its
+// tangent, and one GEMM forms both J x and J dx.  The tangent follows the derivative of
+// eqs. (7), (3), (4), (5) (see the update below); the control strength may differ per
+// replica (a.acol).
 // ---------------------------------------------------------------------------------------
-template <int FORM, bool DISC>
+template <int FORM, bool DISC, bool TANG = false>
 __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
+  static_assert(!TANG || (FORM == kFormFP32 && !DISC), "the tangent needs the continuous binary32 product");
   __shared__ int s_flag;
   __shared__ int s_local;
   constexpr int BM = tile_rows_kind(kKindGeneric);
@@ -341,6 +349,51 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
 
     // Fused update, eqs. (7), (3), (4), (5), in binary32, one rounding per operator.
     const float rm = a.rtab[m];
+    if constexpr (TANG) {
+      // Column tile 0: the replicas; column tile 1: their tangents (dx, dy, dp).  With
+      // f = 1 - A x^2:  dp' = dp (1 - f r) + 2 A x dx p r,
+      // dy' = dy - (dp' x + p' dx) dt + c dt (J dx),  dx' = dx + dy' dt,
+      // and both dx' and dy' are 0 where the wall acts.
+      const float Ar = a.acol ? a.acol[(col0 >> 1) + (lane & 15)] : A;
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float x = xs[rt][0][v], y = ys[rt][0][v], p = ps[rt][0][v];
+          const float tx = xs[rt][1][v], ty = ys[rt][1][v], tp = ps[rt][1][v];
+          const float xx = x * x;
+          const float ax = Ar * xx;
+          const float f = 1.0f - ax;
+          const float fp = f * p;
+          const float dp = fp * rm;
+          const float pn = p - dp;
+          const float px = pn * x;
+          const float pxdt = px * dt;
+          const float y1 = y - pxdt;
+          const float gy = cdt * acc[rt][0][v];
+          const float yn = y1 + gy;
+          const float dxs = yn * dt;
+          const float xn = x + dxs;
+          const bool hit = __builtin_fabsf(xn) > 1.0f;
+          const float fr = f * rm;
+          const float keep = 1.0f - fr;
+          const float ctl = (((2.0f * Ar) * x) * tx) * p;
+          const float tpn = tp * keep + ctl * rm;
+          const float dyp = (tpn * x + pn * tx) * dt;
+          const float tyn = (ty - dyp) + cdt * acc[rt][1][v];
+          const float txn = tx + tyn * dt;
+          xs[rt][0][v] = __builtin_amdgcn_fmed3f(xn, -1.0f, 1.0f);
+          ys[rt][0][v] = hit ? 0.0f : yn;
+          ps[rt][0][v] = pn;
+          xs[rt][1][v] = hit ? 0.0f : txn;
+          ys[rt][1][v] = hit ? 0.0f : tyn;
+          ps[rt][1][v] = tpn;
+        }
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+          store_operand<FORM, DISC>(qnext, plane_bytes, nks, row0 + rt * 16, col0 + ct * 16, lane, xs[rt][ct]);
+      }
+    } else
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
@@ -727,25 +780,129 @@ __device__ __forceinline__ float uniform_pm01(uint64_t z) {
 }
 
 // Initial state: counter (2 r + stream) n + i, draw number counter + 1.
+// Starting x, y of spin i < n of replica r.  Draw counter (2 r + s) n + i for stream s.
+//   mode 0: x ~ U(-0.1, 0.1), y = 0 (App. A);  mode 1: x, y ~ U(-0.1, 0.1);
+//   mode 2: x = +-0.1, y = 0 (Sec. IV);
+//   mode 3: the trajectory pairs of Sec. IV: replica 2k starts at x1 = +-0.1 (counter
+//           (2k) n + i), replica 2k + 1 at x1 +- 2e-6 (sign from counter (2k + 1) n + i),
+//           evaluated in binary64 and rounded once; y = 0.
+__device__ __forceinline__ void init_elem(int n, int r, int i, uint64_t seed, int mode, float& xv, float& yv) {
+  yv = 0.0f;
+  if (mode == 3) {
+    const int k = r >> 1;
+    const uint64_t c0 = (uint64_t)(2 * (int64_t)k) * (uint64_t)n + (uint64_t)i;
+    const float x1 = (splitmix64(seed, c0 + 1) >> 63) ? -0.1f : 0.1f;
+    if (r & 1) {
+      const double d = (splitmix64(seed, c0 + (uint64_t)n + 1) >> 63) ? -2e-6 : 2e-6;
+      xv = (float)((double)x1 + d);
+    } else {
+      xv = x1;
+    }
+    return;
+  }
+  const uint64_t c0 = (uint64_t)(2 * (int64_t)r) * (uint64_t)n + (uint64_t)i;
+  const uint64_t z0 = splitmix64(seed, c0 + 1);
+  if (mode == 2) {
+    xv = (z0 >> 63) ? -0.1f : 0.1f;  // the chaos start of Sec. IV
+  } else {
+    xv = uniform_pm01(z0);
+    if (mode == 1) yv = uniform_pm01(splitmix64(seed, c0 + (uint64_t)n + 1));
+  }
+}
+
 __global__ void k_init_state(int n, int np, int rp, uint64_t seed, int mode, float* x, float* y, float* p) {
   const size_t total = (size_t)rp * np;
   for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
     const int r = (int)(t / np), i = (int)(t % np);
     float xv = 0.0f, yv = 0.0f;
-    if (i < n) {
-      const uint64_t c0 = (uint64_t)(2 * (int64_t)r) * (uint64_t)n + (uint64_t)i;
-      const uint64_t z0 = splitmix64(seed, c0 + 1);
-      if (mode == 2) {
-        xv = (z0 >> 63) ? -0.1f : 0.1f;  // the chaos start of Sec. IV
-      } else {
-        xv = uniform_pm01(z0);
-        if (mode == 1) yv = uniform_pm01(splitmix64(seed, c0 + (uint64_t)n + 1));
-      }
-    }
+    if (i < n) init_elem(n, r, i, seed, mode, xv, yv);
     x[t] = xv;
     y[t] = yv;
     p[t] = 1.0f;  // p_i(0) = 1
   }
+}
+
+// Tangent-mode layout (2 rp columns, blocks of 32: 16 replicas, then their tangents).
+// Replica r starts as k_init_state would start it; its tangent is dx_i = +-1 (bit 63 of
+// draw r n + i + 1 of `tseed`), dy = dp = 0, to be scaled to unit norm.
+__global__ void k_init_tangent(int n, int np, int rp, uint64_t seed, int mode, uint64_t tseed, float* x, float* y,
+                               float* p) {
+  const size_t total = (size_t)2 * rp * np;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+    const int col = (int)(t / np), i = (int)(t % np);
+    const int r = (col >> 5) * 16 + (col & 15);
+    float xv = 0.0f, yv = 0.0f, pv = 1.0f;
+    if ((col & 31) < 16) {
+      if (i < n) init_elem(n, r, i, seed, mode, xv, yv);
+    } else {
+      pv = 0.0f;
+      if (i < n) xv = (splitmix64(tseed, (uint64_t)r * (uint64_t)n + (uint64_t)i + 1) >> 63) ? -1.0f : 1.0f;
+    }
+    x[t] = xv;
+    y[t] = yv;
+    p[t] = pv;
+  }
+}
+
+// Scale each replica's tangent (dx, dy, dp over spins < n) to unit norm; with
+// `accumulate`, add ln of the norm it had to lg[r] (binary64, fixed summation order).
+__global__ void __launch_bounds__(256) k_tangent_renorm(int n, int np, float* x, float* y, float* p, double* lg,
+                                                        int accumulate) {
+  __shared__ double red[4];
+  const int r = blockIdx.x;
+  const size_t o = (size_t)((r >> 4) * 32 + 16 + (r & 15)) * np;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double a = x[o + i], b = y[o + i], c = p[o + i];
+    s += (a * a + b * b) + c * c;
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  s = ((red[0] + red[1]) + red[2]) + red[3];
+  if (s > 0.0) {
+    if (accumulate && threadIdx.x == 0) lg[r] += 0.5 * log(s);
+    const float k = (float)(1.0 / sqrt(s));
+    for (int i = threadIdx.x; i < n; i += 256) {
+      x[o + i] *= k;
+      y[o + i] *= k;
+      p[o + i] *= k;
+    }
+  } else if (accumulate && threadIdx.x == 0) {
+    lg[r] = -INFINITY;  // every component reached a wall: the tangent vanished
+  }
+}
+
+// Tangent-mode state -> [6][R][n] (x, y, p, dx, dy, dp).
+__global__ void k_tangent_extract(int n, int np, int R, const float* x, const float* y, const float* p, float* out) {
+  const size_t total = (size_t)R * n;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)(t / n), i = (int)(t % n);
+    const size_t op = (size_t)((r >> 4) * 32 + (r & 15)) * np + i, ot = op + (size_t)16 * np;
+    out[t] = x[op];
+    out[total + t] = y[op];
+    out[2 * total + t] = p[op];
+    out[3 * total + t] = x[ot];
+    out[4 * total + t] = y[ot];
+    out[5 * total + t] = p[ot];
+  }
+}
+
+// Normalised distance of the trajectory pairs (replicas 2k, 2k + 1) over spins < n, eq. (8).
+__global__ void __launch_bounds__(256) k_delta(int n, int np, const float* x, double* out) {
+  __shared__ double red[4];
+  const int k = blockIdx.x;
+  const float* a = x + (size_t)(2 * k) * np;
+  const float* b = a + np;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double d = (double)a[i] - (double)b[i];
+    s += d * d;
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[k] = sqrt((((red[0] + red[1]) + red[2]) + red[3]) / (4.0 * n));
 }
 
 // Energy, eq. (1): E_r = -1/2 sum_i s_i h_i with h_i = sum_j J_ij s_j, s = sgn(x).
@@ -946,6 +1103,8 @@ const void* steps_kernel_disc(int form, int kind, int np) {
   }
 }
 
+const void* steps_kernel_tangent() { return reinterpret_cast<const void*>(&k_steps<kFormFP32, false, true>); }
+
 const void* steps_kernel_for(int form, int kind, int np, bool discrete) {
   return discrete ? steps_kernel_disc<true>(form, kind, np) : steps_kernel_disc<false>(form, kind, np);
 }
@@ -991,10 +1150,15 @@ int choose_kind(int form, int np) {
   return (form == kFormFP8 && np <= 2048) ? kKindRegJ : kKindGeneric;
 }
 
-int max_coresident_workgroups(int form, int kind, int np) {
+int max_coresident_workgroups(int form, int kind, int np, bool tangent) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (tangent) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, steps_kernel_tangent(), kThreads, 0) != hipSuccess)
+      return 0;
+    return per_cu * cus;
+  }
   int best = 0;
   for (int disc = 0; disc < 2; ++disc) {
     const void* k = steps_kernel_for(form, kind, np, disc != 0);
@@ -1008,8 +1172,9 @@ int max_coresident_workgroups(int form, int kind, int np) {
   return best;
 }
 
-hipError_t launch_steps(int form, int kind, const StepArgs& a, hipStream_t stream) {
-  const void* k = steps_kernel_for(form, kind, a.np, a.discrete != 0);
+hipError_t launch_steps(int form, int kind, const StepArgs& a, hipStream_t stream, bool tangent) {
+  if (tangent && (form != kFormFP32 || kind != kKindGeneric || a.discrete)) return hipErrorInvalidValue;
+  const void* k = tangent ? steps_kernel_tangent() : steps_kernel_for(form, kind, a.np, a.discrete != 0);
   if (!k) return hipErrorInvalidValue;
   const size_t lds = steps_lds_bytes(form, kind, a.np);
   if (lds > 0) {
@@ -1019,6 +1184,31 @@ hipError_t launch_steps(int form, int kind, const StepArgs& a, hipStream_t strea
   StepArgs copy = a;
   void* args[] = {&copy};
   return hipLaunchCooperativeKernel(k, dim3(a.groups * a.nb), dim3(kThreads), args, (unsigned)lds, stream);
+}
+
+hipError_t launch_init_tangent(int n, int np, int rp, uint64_t seed, int mode, uint64_t tseed, float* x, float* y,
+                               float* p, hipStream_t stream) {
+  hipLaunchKernelGGL(k_init_tangent, dim3(grid_for((size_t)2 * rp * np, 256)), dim3(256), 0, stream, n, np, rp, seed,
+                     mode, tseed, x, y, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_tangent_renorm(int n, int np, int rp, float* x, float* y, float* p, double* lg, bool accumulate,
+                                 hipStream_t stream) {
+  hipLaunchKernelGGL(k_tangent_renorm, dim3(rp), dim3(256), 0, stream, n, np, x, y, p, lg, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_tangent_extract(int n, int np, int R, const float* x, const float* y, const float* p, float* out,
+                                  hipStream_t stream) {
+  hipLaunchKernelGGL(k_tangent_extract, dim3(grid_for((size_t)R * n, 256)), dim3(256), 0, stream, n, np, R, x, y, p,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_delta(int n, int np, int pairs, const float* x, double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_delta, dim3(pairs), dim3(256), 0, stream, n, np, x, out);
+  return hipGetLastError();
 }
 
 size_t energy_partial_doubles(int np, int rp) { return (size_t)(np / 256 + 1) * rp; }

@@ -22,7 +22,7 @@ GSB_ENOMEM, GSB_EDEVICE, GSB_ESTATE, GSB_EUNSUPPORTED = -5, -6, -7, -8
 GSB_BSB, GSB_DSB, GSB_GBSB, GSB_GDSB = 0, 1, 2, 3
 GSB_SCHED_LINEAR, GSB_SCHED_CONSTANT = 0, 1
 GSB_PREC_FP32, GSB_PREC_BF16X2, GSB_PREC_FP8 = 0, 1, 2
-GSB_INIT_X, GSB_INIT_XY, GSB_INIT_PM01 = 0, 1, 2
+GSB_INIT_X, GSB_INIT_XY, GSB_INIT_PM01, GSB_INIT_PAIRS = 0, 1, 2, 3
 (GSB_OPT_C, GSB_OPT_PRECISION, GSB_OPT_INIT_MODE, GSB_OPT_LAMBDA_MAX, GSB_OPT_LAMBDA_MIN, GSB_OPT_N,
  GSB_OPT_STEP, GSB_OPT_REPLICAS, GSB_OPT_DT_STABLE, GSB_OPT_N_DYN) = range(10)
 
@@ -35,7 +35,8 @@ STATUS_NAMES = {0: "GSB_OK", -1: "GSB_EINVAL", -2: "GSB_ENOTSYM", -3: "GSB_EDIAG
 # Every symbol include/gsb.h declares.
 SYMBOLS = ("gsb_create", "gsb_destroy", "gsb_set", "gsb_get", "gsb_set_stream", "gsb_workspace_size",
            "gsb_bind_workspace", "gsb_init", "gsb_step", "gsb_run", "gsb_energy", "gsb_best", "gsb_spins",
-           "gsb_state", "gsb_set_state", "gsb_last_step_ms", "gsb_last_error", "gsb_version")
+           "gsb_state", "gsb_set_state", "gsb_delta", "gsb_lle_workspace_size", "gsb_lle", "gsb_last_step_ms",
+           "gsb_last_error", "gsb_version")
 
 
 class GsbError(RuntimeError):
@@ -79,6 +80,9 @@ def load_library(path: str = LIB_PATH):
         "gsb_spins": (i32, [vp, vp]),
         "gsb_state": (i32, [vp, vp, vp, vp, ctypes.POINTER(i32)]),
         "gsb_set_state": (i32, [vp, vp, vp, vp, i32]),
+        "gsb_delta": (i32, [vp, vp]),
+        "gsb_lle_workspace_size": (i32, [vp, i32, i32, ctypes.POINTER(sz)]),
+        "gsb_lle": (i32, [vp, i32, i32, dbl, vp, dbl, i32, i32, u64, u64, i32, vp, vp]),
         "gsb_last_step_ms": (i32, [vp, ctypes.POINTER(dbl)]),
         "gsb_last_error": (ctypes.c_char_p, []),
         "gsb_version": (ctypes.c_char_p, []),
@@ -205,6 +209,36 @@ def gsb_set_state(ctx, x: np.ndarray, y: np.ndarray, p: np.ndarray, m: int) -> N
     _check(load_library().gsb_set_state(ctx, _ptr(x), _ptr(y), _ptr(p), m), "gsb_set_state")
 
 
+def gsb_delta(ctx) -> np.ndarray:
+    R = int(gsb_get(ctx, GSB_OPT_REPLICAS))
+    out = np.empty(max(R // 2, 1), dtype=np.float64)
+    _check(load_library().gsb_delta(ctx, _ptr(out)), "gsb_delta")
+    return out[: R // 2]
+
+
+def gsb_lle_workspace_size(ctx, replicas: int, steps: int) -> int:
+    v = ctypes.c_size_t()
+    _check(load_library().gsb_lle_workspace_size(ctx, replicas, steps, ctypes.byref(v)), "gsb_lle_workspace_size")
+    return v.value
+
+
+def gsb_lle(ctx, variant: int, schedule: int, control_strength: float, A_per_replica, dt: float, replicas: int,
+            steps: int, seed: int, tangent_seed: int, renorm_every: int, want_state: bool = False):
+    """Returns lle[replicas] and, with want_state, the (6, replicas, n_dyn) float32 final state
+    (x, y, p, dx, dy, dp)."""
+    lle = np.empty(replicas, dtype=np.float64)
+    Ar = None if A_per_replica is None else np.ascontiguousarray(A_per_replica, dtype=np.float64)
+    if Ar is not None and Ar.shape != (replicas,):
+        raise ValueError("A_per_replica must have one entry per replica")
+    st = None
+    if want_state:
+        st = np.empty((6, replicas, int(gsb_get(ctx, GSB_OPT_N_DYN))), dtype=np.float32)
+    _check(load_library().gsb_lle(ctx, variant, schedule, control_strength, None if Ar is None else _ptr(Ar), dt,
+                                  replicas, steps, seed & (2**64 - 1), tangent_seed & (2**64 - 1), renorm_every,
+                                  _ptr(lle), None if st is None else _ptr(st)), "gsb_lle")
+    return (lle, st) if want_state else lle
+
+
 def gsb_last_step_ms(ctx) -> float:
     v = ctypes.c_double()
     _check(load_library().gsb_last_step_ms(ctx, ctypes.byref(v)), "gsb_last_step_ms")
@@ -247,9 +281,9 @@ class GSB:
         except Exception:
             pass
 
-    def _prepare(self, replicas: int, steps: int):
+    def _prepare(self, replicas: int, steps: int, lle: bool = False):
         torch = self._torch
-        need = gsb_workspace_size(self.ctx, replicas, steps)
+        need = (gsb_lle_workspace_size if lle else gsb_workspace_size)(self.ctx, replicas, steps)
         if self._ws is None or self._ws.numel() < need + 256:
             self._ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
             base = self._ws.data_ptr()
@@ -287,6 +321,18 @@ class GSB:
 
     def set_state(self, x, y, p, m):
         gsb_set_state(self.ctx, x, y, p, m)
+
+    def delta(self) -> np.ndarray:
+        return gsb_delta(self.ctx)
+
+    def lle(self, variant, *, A=0.0, dt: float, replicas: int, steps: int, seed: int, tangent_seed: int,
+            renorm_every: int = 10, schedule: int = GSB_SCHED_LINEAR, want_state: bool = False):
+        """Largest-Lyapunov-exponent estimates; A is one value or one per replica."""
+        v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        per = None if np.isscalar(A) else np.asarray(A, dtype=np.float64)
+        self._prepare(replicas, steps, lle=True)
+        return gsb_lle(self.ctx, v, schedule, float(A) if per is None else 0.0, per, dt, replicas, steps, seed,
+                       tangent_seed, renorm_every, want_state)
 
     def last_step_ms(self) -> float:
         return gsb_last_step_ms(self.ctx)
