@@ -88,6 +88,48 @@ def cpu_baseline(J, c, target_s: float = 12.0):
                       f"binary32 update) of the N={N} instance, {el:.1f} s"}
 
 
+def chaos_sweeps(J, c):
+    """Edge-of-chaos diagnostics on the same instance (binary32 form, continuous product):
+    LLE estimates for 16 control strengths log-spaced over two decades x 64 replicas in one
+    batched tangent run of 500 steps, and the paper's delta(t_M) (eq. (8)) of 64 trajectory
+    pairs per A of the success sweep after 2000 steps (Sec. IV)."""
+    import numpy as np
+    import torch
+
+    from paper_2508_17655_amd import gsb
+
+    a_vals = [10.0 ** (-2.0 + 2.0 * k / 15.0) for k in range(16)]
+    per = 64
+    A = np.repeat(np.array(a_vals), per)
+    T, renorm = 500, 10
+    g = gsb.GSB(J, precision="fp32", c=c)
+    g.lle("gbsb", A=A[:per], dt=DT, replicas=per, steps=20, seed=1, tangent_seed=2, renorm_every=renorm)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lle = g.lle("gbsb", A=A, dt=DT, replicas=A.size, steps=T, seed=11, tangent_seed=12, renorm_every=renorm)
+    wall = time.perf_counter() - t0
+    dev_ms = g.last_step_ms()
+    g.close()
+    lle = lle.reshape(16, per)
+    fin = np.where(np.isfinite(lle), lle, np.nan)
+    res = {"lle": {"A": a_vals, "mean": [_finite(float(v)) for v in np.nanmean(fin, axis=1)],
+                   "std": [_finite(float(v)) for v in np.nanstd(fin, axis=1)],
+                   "vanished": [int(v) for v in np.sum(~np.isfinite(lle), axis=1)],
+                   "replicas": int(A.size), "steps": T, "renorm_every": renorm, "ms": wall * 1e3,
+                   "device_ms": dev_ms, "n": N, "form": "fp32 (primal and tangent)"}}
+    pairs = 64
+    gp = gsb.GSB(J, precision="fp32", c=c, init_mode=gsb.GSB_INIT_PAIRS)
+    dmean = []
+    t0 = time.perf_counter()
+    for a in [0.0] + A_SWEEP:
+        gp.run("gbsb", A=a, dt=DT, replicas=2 * pairs, steps=M, seed=21)
+        dmean.append(float(np.mean(gp.delta())))
+    res["delta"] = {"A": [0.0] + A_SWEEP, "mean": dmean, "pairs": pairs, "steps": M, "ms": (time.perf_counter() - t0) * 1e3,
+                    "form": "fp32", "chaos_level": 1.0 / math.sqrt(2.0)}
+    gp.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +137,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-sweep", action="store_true", help="skip the P_S/TTS99 sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-chaos", action="store_true", help="skip the LLE and delta sweeps")
     ap.add_argument("--profile", action="store_true", help="few untimed runs only (for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -212,6 +255,8 @@ def main():
                           "tts_semantics": "T_com = one launch of all replicas; P_S of the batch = 1-(1-p_hat)^R",
                           "best_gbsb": best_row, "table": table}
         out["tts99_s"] = best_row["fp8"]["tts99_s"]
+    if not args.no_chaos:
+        out["chaos"] = chaos_sweeps(J, c)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(J.astype(np.float64), c)
     print(json.dumps(out))
