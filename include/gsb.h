@@ -213,6 +213,19 @@ gsb_status gsb_lle(gsb_ctx* ctx, int32_t variant, int32_t schedule, double contr
                    const double* A_per_replica, double dt, int32_t replicas, int32_t steps, uint64_t seed,
                    uint64_t tangent_seed, int32_t renorm_every, double* lle, float* state_out);
 
+/* Reverse derivative (vector-Jacobian product) of the next `count` steps of the current
+ * run, without advancing it: given the cotangents of x, y, p after those steps, return
+ * the cotangents of x, y, p at the current step.  bSB/GbSB runs in the FP32 precision
+ * only (the sign product and the E4M3 rounding are piecewise constant).  The reverse
+ * step is the transpose of the forward derivative documented at gsb_lle; J symmetric,
+ * so it uses the same product.  The library recomputes the `count` steps from the
+ * current state and keeps every step's input state on the device (12 bytes per element
+ * and step, allocated and kept by the context until gsb_destroy): checkpoint long
+ * trajectories in segments (restore each segment's start with gsb_set_state).
+ *   xb, yb, pb : host, replicas * n_dyn binary32 each, replica-major; overwritten.
+ * Synchronises.  Errors: ESTATE, EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE. */
+gsb_status gsb_vjp(gsb_ctx* ctx, int32_t count, float* xb, float* yb, float* pb);
+
 /* Device time of the last gsb_step/gsb_run time stepping (the persistent step kernel
  * launches), in milliseconds, measured with HIP events on the context's stream.
  * Synchronises the stream. */

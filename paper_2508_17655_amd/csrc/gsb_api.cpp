@@ -159,6 +159,8 @@ struct gsb_ctx {
   void* ws_user = nullptr;
   size_t ws_user_bytes = 0;
   void* ws_own = nullptr;
+  void* vjp_buf = nullptr;   // reverse pass: tape and cotangents (library-owned)
+  size_t vjp_bytes = 0;
   size_t ws_own_bytes = 0;
   uint8_t* ws = nullptr;   // current workspace base
   size_t ws_bytes = 0;
@@ -365,10 +367,9 @@ gsb_status gsb_create(const float* J, const float* h, int32_t n, gsb_ctx** out) 
 void gsb_destroy(gsb_ctx* c) {
   if (!c) return;
   // Teardown cannot report errors; a failed synchronisation or free is ignored here.
-  if (c->ws_own) {
-    (void)hipStreamSynchronize(c->stream);
-    (void)hipFree(c->ws_own);
-  }
+  if (c->ws_own || c->vjp_buf) (void)hipStreamSynchronize(c->stream);
+  if (c->ws_own) (void)hipFree(c->ws_own);
+  if (c->vjp_buf) (void)hipFree(c->vjp_buf);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   delete c;
@@ -521,9 +522,12 @@ gsb_status carve_and_prepare(gsb_ctx* c, const Layout& L, int kind, int form, in
 // Persistent step launches for steps [m0, m1) over `cols` columns of the current
 // buffers, in chunks of c->chunk_rp columns.
 gsb_status launch_chunks(gsb_ctx* c, int form, int cols, bool discrete, float A, const float* acol, int m0, int m1,
-                         bool tangent) {
-  for (int r0 = 0; r0 < cols; r0 += c->chunk_rp) {
-    const int rcount = std::min(c->chunk_rp, cols - r0);
+                         bool tangent, float* X = nullptr, float* Y = nullptr, float* P = nullptr,
+                         float* tape = nullptr, bool adjoint = false, int chunk = 0) {
+  if (!X) { X = c->X; Y = c->Y; P = c->P; }
+  if (chunk <= 0) chunk = c->chunk_rp;
+  for (int r0 = 0; r0 < cols; r0 += chunk) {
+    const int rcount = std::min(chunk, cols - r0);
     StepArgs a;
     a.n = c->n;
     a.np = c->np;
@@ -541,13 +545,19 @@ gsb_status launch_chunks(gsb_ctx* c, int form, int cols, bool discrete, float A,
     a.jf = c->jf;
     a.q = c->Q;
     a.q_buf_bytes = (size_t)rcount * c->np * operand_elem_bytes(form) * operand_planes(form);
-    a.x = c->X + (size_t)r0 * c->np;
-    a.y = c->Y + (size_t)r0 * c->np;
-    a.p = c->P + (size_t)r0 * c->np;
+    a.x = X + (size_t)r0 * c->np;
+    a.y = Y + (size_t)r0 * c->np;
+    a.p = P + (size_t)r0 * c->np;
     a.sync = c->sync;
     a.status = c->status;
+    a.tape = tape ? tape + (size_t)r0 * c->np : nullptr;
+    a.tape_arr = (size_t)cols * c->np;
     HIP_TRY(launch_fill_u32(c->sync, sync_words(a.groups), 0u, c->stream), "clear sync");
-    HIP_TRY(launch_steps(form, c->kind, a, c->stream, tangent), "step kernel launch");
+    if (adjoint) {
+      HIP_TRY(launch_adjoint(a, c->stream), "adjoint kernel launch");
+    } else {
+      HIP_TRY(launch_steps(form, c->kind, a, c->stream, tangent), "step kernel launch");
+    }
   }
   return GSB_OK;
 }
@@ -806,6 +816,63 @@ gsb_status gsb_lle(gsb_ctx* c, int32_t variant, int32_t schedule, double A, cons
   if (s != GSB_OK) return s;
   for (int r = 0; r < replicas; ++r) lle[r] = lg_host[r] / ((double)steps * dt);
   return GSB_OK;
+}
+
+gsb_status gsb_vjp(gsb_ctx* c, int32_t count, float* xb, float* yb, float* pb) {
+  g_err.clear();
+  if (!c || !xb || !yb || !pb) return fail(GSB_EINVAL, "NULL argument");
+  if (!c->inited) return fail(GSB_ESTATE, "no run");
+  if (c->variant != GSB_BSB && c->variant != GSB_GBSB)
+    return fail(GSB_EINVAL, "the reverse pass needs a continuous product (bSB or GbSB)");
+  if (c->precision != GSB_PREC_FP32 || c->kind != kKindGeneric)
+    return fail(GSB_EUNSUPPORTED, "the reverse pass runs in the FP32 form (set GSB_OPT_PRECISION before the run)");
+  if (count < 1 || c->m + count > c->M) return fail(GSB_EINVAL, "count must be >= 1 and stay within the schedule");
+  const size_t arr = (size_t)c->rp * c->np;
+  const size_t need = ((size_t)3 * (count + 1) + 3) * arr * 4;
+  if (need > c->vjp_bytes) {
+    if (c->vjp_buf) {
+      const hipError_t es = hipStreamSynchronize(c->stream);
+      const hipError_t ef = hipFree(c->vjp_buf);
+      c->vjp_buf = nullptr;
+      c->vjp_bytes = 0;
+      if (es != hipSuccess || ef != hipSuccess) return fail(GSB_EDEVICE, "releasing the reverse-pass buffer");
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, need) != hipSuccess) return fail(GSB_ENOMEM, "reverse-pass buffer of " + std::to_string(need) + " bytes");
+    c->vjp_buf = p;
+    c->vjp_bytes = need;
+  }
+  float* tape = static_cast<float*>(c->vjp_buf);
+  float* last = tape + (size_t)3 * count * arr;  // entry `count`: the state after the segment
+  float* cot = tape + (size_t)3 * (count + 1) * arr;
+  // forward again from the current state, recording every step's input
+  HIP_TRY(hipMemcpyAsync(last, c->X, arr * 4, hipMemcpyDeviceToDevice, c->stream), "copy state");
+  HIP_TRY(hipMemcpyAsync(last + arr, c->Y, arr * 4, hipMemcpyDeviceToDevice, c->stream), "copy state");
+  HIP_TRY(hipMemcpyAsync(last + 2 * arr, c->P, arr * 4, hipMemcpyDeviceToDevice, c->stream), "copy state");
+  gsb_status s = launch_chunks(c, kFormFP32, c->rp, false, (float)c->A, nullptr, c->m, c->m + count, false, last,
+                               last + arr, last + 2 * arr, tape);
+  if (s != GSB_OK) return s;
+  // cotangents in, reverse pass, cotangents out
+  const int nd = c->n;
+  HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(cot), 3 * arr, 0u, c->stream), "clear cotangents");
+  const float* src[3] = {xb, yb, pb};
+  for (int k = 0; k < 3; ++k)
+    HIP_TRY(hipMemcpy2DAsync(cot + k * arr, (size_t)c->np * 4, src[k], (size_t)nd * 4, (size_t)nd * 4, c->R,
+                             hipMemcpyHostToDevice, c->stream),
+            "upload cotangents");
+  const int max_wg = max_coresident_adjoint();
+  const int nb = c->np / tile_rows_kind(kKindGeneric);
+  const int chunk = std::min(c->rp, std::max(max_wg / nb, 0) * tile_cols_kind(kKindGeneric) / kRepPad * kRepPad);
+  if (chunk < kRepPad) return fail(GSB_EUNSUPPORTED, "n too large for one co-resident replica block (reverse pass)");
+  s = launch_chunks(c, kFormFP32, c->rp, false, (float)c->A, nullptr, c->m, c->m + count, false, cot, cot + arr,
+                    cot + 2 * arr, tape, true, chunk);
+  if (s != GSB_OK) return s;
+  float* dst[3] = {xb, yb, pb};
+  for (int k = 0; k < 3; ++k)
+    HIP_TRY(hipMemcpy2DAsync(dst[k], (size_t)nd * 4, cot + k * arr, (size_t)c->np * 4, (size_t)nd * 4, c->R,
+                             hipMemcpyDeviceToHost, c->stream),
+            "download cotangents");
+  return check_status_word(c);
 }
 
 gsb_status gsb_last_step_ms(gsb_ctx* c, double* ms) {

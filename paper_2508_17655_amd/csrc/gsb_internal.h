@@ -55,6 +55,8 @@ struct StepArgs {
   float* x; float* y; float* p;  // state of this launch's replicas, [rp][np]
   unsigned* sync;         // zeroed before the launch; see sync_words()
   unsigned* status;       // set nonzero on a device-side timeout
+  float* tape = nullptr;  // binary32 form: per-step input states (reverse pass), or nullptr
+  size_t tape_arr = 0;    // floats between the x, y, p planes of one tape entry
 };
 
 inline size_t sync_words(int groups) { return (size_t)(4 * groups + 1) * 64; }
@@ -69,6 +71,10 @@ hipError_t launch_init_state(int n, int np, int rp, uint64_t seed, int mode, flo
 // blocks of 32 = 16 replicas followed by their 16 tangents.
 hipError_t launch_steps(int form, int kind, const StepArgs& a, hipStream_t stream, bool tangent = false);
 int max_coresident_workgroups(int form, int kind, int np, bool tangent = false);
+// Reverse pass of the binary32 dynamics over a recorded tape (see k_adjoint); a.x, a.y,
+// a.p carry the cotangents in and out.  Occupancy limit of that kernel.
+hipError_t launch_adjoint(const StepArgs& a, hipStream_t stream);
+int max_coresident_adjoint();
 // Tangent mode: starting state (as launch_init_state for each replica) and tangent
 // dx = +-1 from `tseed` (dy = dp = 0) for rp replicas in 2 rp columns.
 hipError_t launch_init_tangent(int n, int np, int rp, uint64_t seed, int mode, uint64_t tseed, float* x, float* y,

@@ -139,6 +139,34 @@ __device__ __forceinline__ void store_operand(uint8_t* qbuf, size_t plane_bytes,
   }
 }
 
+// One wave's 64 x 32 tile of G = J Q in the binary32 form: 4 row tiles (J rows, `jrows`)
+// x 2 column tiles (Q blocks rb0, rb0 + 1 of the buffer behind `qr`) of 16x16x4 MFMAs.
+__device__ __forceinline__ void gemm_tile_fp32(const uint8_t* jrows, __amdgpu_buffer_rsrc_t qr, int rb0, int nks,
+                                               int lane, v4f (&acc)[4][2]) {
+  for (int ks = 0; ks < nks; ++ks) {
+    for (int grp = 0; grp < 8; ++grp) {
+      v4f aj[4], bq[2];
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) {
+        const size_t o = ((size_t)(rt * nks + ks) * 8 + grp) * 1024 + lane * 16;
+        aj[rt] = *reinterpret_cast<const v4f*>(jrows + o);
+      }
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        const unsigned base = (unsigned)(((size_t)((rb0 + ct) * nks + ks) * 8 + grp) * 1024 + lane * 16);
+        bq[ct] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kPolicySc1));
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct)
+            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(aj[rt][t], bq[ct][t], acc[rt][ct], 0, 0, 0);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // Generic persistent step kernel (any product form; J fragments read from L2).
 // Workgroup (g, mb) owns spins [64 mb, 64 mb + 64) of replicas [128 g, 128 g + 128); each
@@ -323,28 +351,7 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
         }
       }
     } else {  // FP32
-      for (int ks = 0; ks < nks; ++ks) {
-        for (int grp = 0; grp < 8; ++grp) {
-          v4f aj[4], bq[2];
-#pragma unroll
-          for (int rt = 0; rt < 4; ++rt) {
-            const size_t o = ((size_t)(rt * nks + ks) * 8 + grp) * 1024 + lane * 16;
-            aj[rt] = *reinterpret_cast<const v4f*>(jrows + o);
-          }
-#pragma unroll
-          for (int ct = 0; ct < 2; ++ct) {
-            const unsigned base = (unsigned)(((size_t)((rb0 + ct) * nks + ks) * 8 + grp) * 1024 + lane * 16);
-            bq[ct] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kPolicySc1));
-          }
-#pragma unroll
-          for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-              for (int ct = 0; ct < 2; ++ct)
-                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(aj[rt][t], bq[ct][t], acc[rt][ct], 0, 0, 0);
-        }
-      }
+      gemm_tile_fp32(jrows, qr, rb0, nks, lane, acc);
     }
 
     // Fused update, eqs. (7), (3), (4), (5), in binary32, one rounding per operator.
@@ -393,7 +400,19 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
         for (int ct = 0; ct < 2; ++ct)
           store_operand<FORM, DISC>(qnext, plane_bytes, nks, row0 + rt * 16, col0 + ct * 16, lane, xs[rt][ct]);
       }
-    } else
+    } else {
+    if (a.tape) {  // record this step's input state (reverse pass)
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          const size_t o = (size_t)(col0 + ct * 16 + (lane & 15)) * a.np + row0 + rt * 16 + 4 * (lane >> 4);
+          float* t = a.tape + (size_t)3 * s * a.tape_arr + o;
+          *reinterpret_cast<v4f*>(t) = v4f{xs[rt][ct][0], xs[rt][ct][1], xs[rt][ct][2], xs[rt][ct][3]};
+          *reinterpret_cast<v4f*>(t + a.tape_arr) = v4f{ys[rt][ct][0], ys[rt][ct][1], ys[rt][ct][2], ys[rt][ct][3]};
+          *reinterpret_cast<v4f*>(t + 2 * a.tape_arr) = v4f{ps[rt][ct][0], ps[rt][ct][1], ps[rt][ct][2], ps[rt][ct][3]};
+        }
+    }
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
@@ -423,6 +442,7 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
         }
         store_operand<FORM, DISC>(qnext, plane_bytes, nks, row0 + rt * 16, col0 + ct * 16, lane, xs[rt][ct]);
       }
+    }
     alive = group_sync(ctr, (unsigned)((s + 2) * a.nb), local, abort_flag, a.status, &s_flag);
   }
 
@@ -436,6 +456,149 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
       *reinterpret_cast<v4f*>(a.x + o) = v4f{xs[rt][ct][0], xs[rt][ct][1], xs[rt][ct][2], xs[rt][ct][3]};
       *reinterpret_cast<v4f*>(a.y + o) = v4f{ys[rt][ct][0], ys[rt][ct][1], ys[rt][ct][2], ys[rt][ct][3]};
       *reinterpret_cast<v4f*>(a.p + o) = v4f{ps[rt][ct][0], ps[rt][ct][1], ps[rt][ct][2], ps[rt][ct][3]};
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Reverse pass (vector-Jacobian product) of the binary32 dynamics, bSB / GbSB.
+//
+// Same tiling and barrier as k_steps.  The registers hold the cotangents (xb, yb, pb) of
+// the wave's 64 x 32 elements; a.x, a.y, a.p bring them in (cotangents of the state
+// after the last step) and take them out (of the state before the first).  tape entry s
+// (0 <= s <= steps) holds x, y, p at the input of step m_begin + s, entry `steps` the
+// state after the last step.  Step s, from the last one down (J symmetric, so the
+// transposed product is the same GEMM), with k the step's wall mask (the next state has
+// |x| = 1 and y = 0), f = 1 - A x^2, r = r_m and p' the next state's p:
+//   w   = (1 - k) (yb + dt xb)          -- the product operand, G = J w
+//   pb' = pb - dt x w
+//   xb  = (1 - k) xb - dt p' w + c dt G + 2 A x p r pb'
+//   yb  = w,   pb = pb' (1 - f r).
+// This is the transpose of the forward derivative of eqs. (7), (3), (4), (5).
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads, 1) k_adjoint(StepArgs a) {
+  __shared__ int s_flag;
+  __shared__ int s_local;
+  constexpr int BM = tile_rows_kind(kKindGeneric);
+  constexpr int BN = tile_cols_kind(kKindGeneric);
+  constexpr int WCOLS = BN / kWaveCols;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = blockIdx.x % a.groups;
+  const int mb = blockIdx.x / a.groups;
+  const int wrow = wave / WCOLS;
+  const int row0 = mb * BM + wrow * kWaveRows;
+  const int col0 = g * BN + (wave % WCOLS) * kWaveCols;
+  const int nks = a.np / kKS;
+  unsigned* ctr = a.sync + (size_t)g * 64;
+  unsigned* hs = a.sync + (size_t)(a.groups + g) * 64;
+  unsigned* msk = a.sync + (size_t)(2 * a.groups + g) * 64;
+  unsigned* abort_flag = a.sync + (size_t)(3 * a.groups) * 64;
+  const uint8_t* jrows = static_cast<const uint8_t*>(a.jf) + (size_t)(mb * BM / 16 + 4 * wrow) * nks * 8192;
+  auto off = [&](int rt, int ct) {
+    return (size_t)(col0 + ct * 16 + (lane & 15)) * a.np + row0 + rt * 16 + 4 * (lane >> 4);
+  };
+  auto tape = [&](int s, int k, int rt, int ct) {
+    return *reinterpret_cast<const v4f*>(a.tape + (size_t)(3 * s + k) * a.tape_arr + off(rt, ct));
+  };
+
+  float xb[4][2][4], yb[4][2][4], pb[4][2][4], w[4][2][4];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const v4f vx = *reinterpret_cast<const v4f*>(a.x + off(rt, ct));
+      const v4f vy = *reinterpret_cast<const v4f*>(a.y + off(rt, ct));
+      const v4f vp = *reinterpret_cast<const v4f*>(a.p + off(rt, ct));
+#pragma unroll
+      for (int v = 0; v < 4; ++v) { xb[rt][ct][v] = vx[v]; yb[rt][ct][v] = vy[v]; pb[rt][ct][v] = vp[v]; }
+    }
+
+  if (tid == 0) {
+    const unsigned xcc = (unsigned)__builtin_amdgcn_s_getreg(kHwRegXccId) & 15u;
+    __hip_atomic_fetch_or(msk, 1u << xcc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(hs, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    unsigned spins = 0;
+    while (ld_dev(hs) < (unsigned)a.nb) {
+      ++spins;
+      if ((spins & 63u) == 0 && ld_dev(abort_flag)) { ok = 0; break; }
+      if (spins > kSpinLimit) { st_dev(abort_flag, 1u); st_dev(a.status, 1u); ok = 0; break; }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    s_local = (__builtin_popcount(ld_dev(msk)) == 1) ? 1 : 0;
+    s_flag = ok;
+  }
+  __syncthreads();
+  bool alive = s_flag != 0;
+  const int local = s_local;
+  const float A = a.A, dt = a.dt, cdt = a.cdt;
+  const int steps = a.m_end - a.m_begin;
+
+  // w of step s from the current cotangents and the state after step s, published as
+  // the product operand in ping-pong buffer `buf`
+  auto publish_w = [&](int s, int buf) {
+    uint8_t* q = a.q + (size_t)buf * a.q_buf_bytes;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        const v4f xn = tape(s + 1, 0, rt, ct), yn = tape(s + 1, 1, rt, ct);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const bool k = __builtin_fabsf(xn[v]) == 1.0f && yn[v] == 0.0f;
+          w[rt][ct][v] = k ? 0.0f : yb[rt][ct][v] + dt * xb[rt][ct][v];
+        }
+        store_operand<kFormFP32, false>(q, a.q_buf_bytes, nks, row0 + rt * 16, col0 + ct * 16, lane, w[rt][ct]);
+      }
+  };
+
+  if (alive && steps > 0) {
+    publish_w(steps - 1, 0);
+    alive = group_sync(ctr, (unsigned)a.nb, local, abort_flag, a.status, &s_flag);
+  }
+  for (int it = 0; alive && it < steps; ++it) {
+    const int s = steps - 1 - it;
+    const uint8_t* qcur = a.q + (size_t)(it & 1) * a.q_buf_bytes;
+    const __amdgpu_buffer_rsrc_t qr = make_rsrc(qcur, a.q_buf_bytes);
+    v4f acc[4][2];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    gemm_tile_fp32(jrows, qr, col0 >> 4, nks, lane, acc);
+    const float rm = a.rtab[a.m_begin + s];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        const v4f x = tape(s, 0, rt, ct), p = tape(s, 2, rt, ct), xn = tape(s + 1, 0, rt, ct);
+        const v4f yn = tape(s + 1, 1, rt, ct), pn = tape(s + 1, 2, rt, ct);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const bool k = __builtin_fabsf(xn[v]) == 1.0f && yn[v] == 0.0f;
+          const float wv = w[rt][ct][v];
+          const float f = 1.0f - A * (x[v] * x[v]);
+          const float pbn = pb[rt][ct][v] - (dt * x[v]) * wv;
+          const float ctl = (((2.0f * A) * x[v]) * p[v]) * rm;
+          const float xk = k ? 0.0f : xb[rt][ct][v];
+          xb[rt][ct][v] = ((xk - (dt * pn[v]) * wv) + cdt * acc[rt][ct][v]) + ctl * pbn;
+          yb[rt][ct][v] = wv;
+          pb[rt][ct][v] = pbn * (1.0f - f * rm);
+        }
+      }
+    if (s > 0) {
+      publish_w(s - 1, (it + 1) & 1);
+      alive = group_sync(ctr, (unsigned)((it + 2) * a.nb), local, abort_flag, a.status, &s_flag);
+    }
+  }
+
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      *reinterpret_cast<v4f*>(a.x + off(rt, ct)) = v4f{xb[rt][ct][0], xb[rt][ct][1], xb[rt][ct][2], xb[rt][ct][3]};
+      *reinterpret_cast<v4f*>(a.y + off(rt, ct)) = v4f{yb[rt][ct][0], yb[rt][ct][1], yb[rt][ct][2], yb[rt][ct][3]};
+      *reinterpret_cast<v4f*>(a.p + off(rt, ct)) = v4f{pb[rt][ct][0], pb[rt][ct][1], pb[rt][ct][2], pb[rt][ct][3]};
     }
 }
 
@@ -1170,6 +1333,24 @@ int max_coresident_workgroups(int form, int kind, int np, bool tangent) {
     best = disc == 0 ? per_cu * cus : std::min(best, per_cu * cus);
   }
   return best;
+}
+
+hipError_t launch_adjoint(const StepArgs& a, hipStream_t stream) {
+  if (!a.tape) return hipErrorInvalidValue;
+  StepArgs copy = a;
+  void* args[] = {&copy};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_adjoint), dim3(a.groups * a.nb), dim3(kThreads),
+                                    args, 0u, stream);
+}
+
+int max_coresident_adjoint() {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_adjoint), kThreads, 0) !=
+      hipSuccess)
+    return 0;
+  return per_cu * cus;
 }
 
 hipError_t launch_steps(int form, int kind, const StepArgs& a, hipStream_t stream, bool tangent) {

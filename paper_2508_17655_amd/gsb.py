@@ -35,7 +35,7 @@ STATUS_NAMES = {0: "GSB_OK", -1: "GSB_EINVAL", -2: "GSB_ENOTSYM", -3: "GSB_EDIAG
 # Every symbol include/gsb.h declares.
 SYMBOLS = ("gsb_create", "gsb_destroy", "gsb_set", "gsb_get", "gsb_set_stream", "gsb_workspace_size",
            "gsb_bind_workspace", "gsb_init", "gsb_step", "gsb_run", "gsb_energy", "gsb_best", "gsb_spins",
-           "gsb_state", "gsb_set_state", "gsb_delta", "gsb_lle_workspace_size", "gsb_lle", "gsb_last_step_ms",
+           "gsb_state", "gsb_set_state", "gsb_delta", "gsb_lle_workspace_size", "gsb_lle", "gsb_vjp", "gsb_last_step_ms",
            "gsb_last_error", "gsb_version")
 
 
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH):
         "gsb_delta": (i32, [vp, vp]),
         "gsb_lle_workspace_size": (i32, [vp, i32, i32, ctypes.POINTER(sz)]),
         "gsb_lle": (i32, [vp, i32, i32, dbl, vp, dbl, i32, i32, u64, u64, i32, vp, vp]),
+        "gsb_vjp": (i32, [vp, i32, vp, vp, vp]),
         "gsb_last_step_ms": (i32, [vp, ctypes.POINTER(dbl)]),
         "gsb_last_error": (ctypes.c_char_p, []),
         "gsb_version": (ctypes.c_char_p, []),
@@ -239,6 +240,13 @@ def gsb_lle(ctx, variant: int, schedule: int, control_strength: float, A_per_rep
     return (lle, st) if want_state else lle
 
 
+def gsb_vjp(ctx, count: int, xb: np.ndarray, yb: np.ndarray, pb: np.ndarray):
+    """Cotangents at the current step from those `count` steps later (new arrays)."""
+    xb, yb, pb = (np.array(v, dtype=np.float32, order="C", copy=True) for v in (xb, yb, pb))
+    _check(load_library().gsb_vjp(ctx, count, _ptr(xb), _ptr(yb), _ptr(pb)), "gsb_vjp")
+    return xb, yb, pb
+
+
 def gsb_last_step_ms(ctx) -> float:
     v = ctypes.c_double()
     _check(load_library().gsb_last_step_ms(ctx, ctypes.byref(v)), "gsb_last_step_ms")
@@ -333,6 +341,10 @@ class GSB:
         self._prepare(replicas, steps, lle=True)
         return gsb_lle(self.ctx, v, schedule, float(A) if per is None else 0.0, per, dt, replicas, steps, seed,
                        tangent_seed, renorm_every, want_state)
+
+    def vjp(self, count: int, xb, yb, pb):
+        gsb_set_stream(self.ctx, self._torch.cuda.current_stream().cuda_stream)
+        return gsb_vjp(self.ctx, count, xb, yb, pb)
 
     def last_step_ms(self) -> float:
         return gsb_last_step_ms(self.ctx)
