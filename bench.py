@@ -27,6 +27,7 @@ N, R, M, DT, A_HEAD, SEED_J = 2000, 1024, 2000, 1.25, 0.2, 2
 A_SWEEP = [0.05, 0.10, 0.15, 0.20, 0.25, 0.30, 0.35, 0.40]
 FP8_PEAK = 5.0e15      # MI355X dense FP8 MFMA, FLOP/s
 FP32_MFMA_PEAK = 157.3e12
+INT8_PEAK = 5.0e15     # dense int8 MFMA, OP/s
 
 
 def tts99(t_com: float, p_run: float) -> float:
@@ -206,6 +207,23 @@ def main():
                  "kernel_ms": float(np.mean(k32)),
                  "mfma_frac": flop / (float(np.mean(k32)) * 1e-3) / FP32_MFMA_PEAK}
 
+    # ---- the 16-bit fixed-point form (exact continuous product, two int8 passes) ----
+    g16 = gsb.GSB(J, precision="fix16", c=c)
+    g16.run("gbsb", A=A_HEAD, dt=DT, replicas=R, steps=M, seed=998)
+    g16.best()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k16 = []
+    for s in range(nrep32):
+        g16.run("gbsb", A=A_HEAD, dt=DT, replicas=R, steps=M, seed=3100 + s)
+        g16.best()
+        k16.append(g16.last_step_ms())
+    torch.cuda.synchronize()
+    ms16 = 1000 * (time.perf_counter() - t1) / nrep32
+    fix16_form = {"value": R * N * M / (ms16 * 1e-3), "unit": "replica-spin-steps/s", "ms_per_run": ms16,
+                  "kernel_ms": float(np.mean(k16)),
+                  "int8_mfma_frac": 2 * flop / (float(np.mean(k16)) * 1e-3) / INT8_PEAK}
+
     out = {
         "metric": "replica-spin-steps/s (GSB = GbSB, FP8 E4M3 product) at N=2000 dense +-1; TTS99; FP8 vs FP32 form",
         "value": rss,
@@ -223,6 +241,7 @@ def main():
                                f"dt={DT}, c=1/(2 sqrt N), FP8 E4M3 product, binary32 update",
                    "n": N, "replicas": R, "steps_per_run": M, "dt": DT, "A": A_HEAD, "instance_seed": SEED_J},
         "fp32_form": fp32_form,
+        "fix16_form": fix16_form,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP8_PEAK / 1e12, "unit": "TFLOP/s",
                      "frac": achieved * 1e12 / FP8_PEAK, "traffic": load_traffic("k_steps_rj_fp8_n2000_r1024_counters.json"),
                      "kernel": "k_steps_rj<16> (FP8 product, J resident in registers)", "kernel_ms_per_launch": k_ms,
@@ -232,8 +251,8 @@ def main():
     # ---- success probability and TTS99 (Sec. VI definitions), FP8 vs FP32 form ----
     if not args.no_sweep:
         runs = []
-        t_com = {"fp8": ms_per_step * 1e-3, "fp32": ms32 * 1e-3}
-        for form, g in (("fp8", g8), ("fp32", g32)):
+        t_com = {"fp8": ms_per_step * 1e-3, "fp32": ms32 * 1e-3, "fix16": ms16 * 1e-3}
+        for form, g in (("fp8", g8), ("fp32", g32), ("fix16", g16)):
             for variant, A in [("bsb", 0.0)] + [("gbsb", a) for a in A_SWEEP]:
                 g.run(variant, A=A, dt=DT, replicas=R, steps=M, seed=5000)
                 runs.append((form, variant, A, g.energy()))
@@ -250,7 +269,7 @@ def main():
                           "mean": float(E.mean()),
                           "tts99_s": _finite(tts99(t_com[form], p_run))})
         best_row = {f: max((t for t in table if t["form"] == f and t["variant"] == "gbsb"), key=lambda t: t["p_hat"])
-                    for f in ("fp8", "fp32")}
+                    for f in ("fp8", "fp32", "fix16")}
         out["success"] = {"e_star": e_star, "cut_star": -0.5 * (float(np.triu(J, 1).sum()) + e_star),
                           "tts_semantics": "T_com = one launch of all replicas; P_S of the batch = 1-(1-p_hat)^R",
                           "best_gbsb": best_row, "table": table}

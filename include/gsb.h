@@ -65,8 +65,12 @@ typedef enum { GSB_SCHED_LINEAR = 0, GSB_SCHED_CONSTANT = 1 } gsb_schedule;
  *   FP8    : J and q in OCP E4M3 on MFMA, binary32 accumulation.  Requires J_ij in
  *            {0, +1, -1}.  Sign operands (dSB, GdSB) are exact, so the product is exact;
  *            continuous operands (bSB, GbSB) are rounded to E4M3 (nearest even), and the
- *            product of the rounded values is exact. */
-typedef enum { GSB_PREC_FP32 = 0, GSB_PREC_BF16X2 = 1, GSB_PREC_FP8 = 2 } gsb_precision;
+ *            product of the rounded values is exact.
+ *   FIX16  : 16-bit fixed point, the FPGA's JX precision (App. C): q = rint(x 2^14) / 2^14
+ *            (round half to even), J in int8; two int8 MFMA passes (q = 256 hi + lo) with
+ *            exact int32 accumulation, the sum rounded to binary32 once.  Requires J_ij in
+ *            {0, +1, -1}.  An exact continuous product with 14 fraction bits. */
+typedef enum { GSB_PREC_FP32 = 0, GSB_PREC_BF16X2 = 1, GSB_PREC_FP8 = 2, GSB_PREC_FIX16 = 3 } gsb_precision;
 
 /* Initial conditions (drawn on the device from the run seed with counter-based
  * SplitMix64, one counter per (replica, stream, spin); replica r's start does not

@@ -37,9 +37,16 @@ gsb_status hip_fail(hipError_t e, const char* what) {
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 int form_of(int precision) {
-  return precision == GSB_PREC_FP8 ? kFormFP8 : (precision == GSB_PREC_BF16X2 ? kFormBF16X2 : kFormFP32);
+  switch (precision) {
+    case GSB_PREC_FP8: return kFormFP8;
+    case GSB_PREC_BF16X2: return kFormBF16X2;
+    case GSB_PREC_FIX16: return kFormFIX16;
+    default: return kFormFP32;
+  }
 }
-size_t operand_elem_bytes(int form) { return form == kFormFP8 ? 1 : (form == kFormBF16X2 ? 2 : 4); }
+size_t operand_elem_bytes(int form) {
+  return (form == kFormFP8 || form == kFormFIX16) ? 1 : (form == kFormBF16X2 ? 2 : 4);
+}
 
 // ---- eigenvalue bounds of a symmetric matrix (App. A needs lambda_max and lambda_min) ----
 // Lanczos with full reorthogonalisation, binary64; extreme Ritz values of the tridiagonal
@@ -386,9 +393,9 @@ gsb_status gsb_set(gsb_ctx* c, int32_t option, double v) {
       return GSB_OK;
     case GSB_OPT_PRECISION: {
       const int p = (int)v;
-      if ((double)p != v || p < GSB_PREC_FP32 || p > GSB_PREC_FP8) return fail(GSB_EINVAL, "unknown precision");
-      if (p == GSB_PREC_FP8 && !c->pm1)
-        return fail(GSB_EUNSUPPORTED, "FP8 precision needs J entries in {0, +1, -1}");
+      if ((double)p != v || p < GSB_PREC_FP32 || p > GSB_PREC_FIX16) return fail(GSB_EINVAL, "unknown precision");
+      if ((p == GSB_PREC_FP8 || p == GSB_PREC_FIX16) && !c->pm1)
+        return fail(GSB_EUNSUPPORTED, "FP8 and FIX16 precisions need J entries in {0, +1, -1}");
       if (p != c->precision) {
         c->precision = p;
         c->inited = false;  // operand buffers change shape
@@ -574,7 +581,8 @@ gsb_status gsb_init(gsb_ctx* c, int32_t variant, int32_t schedule, double A, dou
   if (!std::isfinite(dt) || dt <= 0) return fail(GSB_EINVAL, "dt must be finite and > 0");
   if (replicas < 1 || replicas > (1 << 20)) return fail(GSB_EINVAL, "replicas must be in [1, 2^20]");
   if (steps < 1 || steps > (1 << 24)) return fail(GSB_EINVAL, "steps must be in [1, 2^24]");
-  if (c->precision == GSB_PREC_FP8 && !c->pm1) return fail(GSB_EUNSUPPORTED, "FP8 precision needs J in {0, +-1}");
+  if ((c->precision == GSB_PREC_FP8 || c->precision == GSB_PREC_FIX16) && !c->pm1)
+    return fail(GSB_EUNSUPPORTED, "FP8 and FIX16 precisions need J in {0, +-1}");
   if (!c->c_set) {
     ensure_eig(c);
     c->c = c->lmax > 0 ? 1.0 / c->lmax : 1.0;  // App. A: c = 1 / lambda_max

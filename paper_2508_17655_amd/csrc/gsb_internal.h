@@ -18,7 +18,9 @@ constexpr int kThreads = 256;
 constexpr int kKStepsUnroll = 4;  // k-steps per software-pipeline round
 constexpr int kRowPad = kKS * kKStepsUnroll;  // np is a multiple of this (512)
 
-enum Form { kFormFP32 = 0, kFormBF16X2 = 1, kFormFP8 = 2 };
+// FIX16: 16-bit fixed point, q = rint(x 2^14) split into int8 hi/lo planes
+// (q = 256 hi + lo), J in int8, two int8 MFMA passes with exact int32 accumulation.
+enum Form { kFormFP32 = 0, kFormBF16X2 = 1, kFormFP8 = 2, kFormFIX16 = 3 };
 
 // Step-kernel variants.
 //   kKindRegJ : FP8 product, np <= 2048: J rows in registers (FP4), 256 spins x 32 replicas
@@ -33,10 +35,12 @@ __host__ __device__ constexpr int tile_cols_kind(int kind) { return 8192 / tile_
 // (16-row tile, k-step), in the fragment-major layouts.  (The register-resident FP8 path
 // stores J as FP4 (E2M1), 1 KiB per block, which holds 0 and +-1 exactly.)
 __host__ __device__ constexpr size_t operand_block_bytes(int form) {
-  return form == kFormFP8 ? 2048 : (form == kFormBF16X2 ? 4096 : 8192);
+  return (form == kFormFP8 || form == kFormFIX16) ? 2048 : (form == kFormBF16X2 ? 4096 : 8192);
 }
 
-__host__ __device__ constexpr int operand_planes(int form) { return form == kFormBF16X2 ? 2 : 1; }
+__host__ __device__ constexpr int operand_planes(int form) {
+  return (form == kFormBF16X2 || form == kFormFIX16) ? 2 : 1;
+}
 
 struct StepArgs {
   int n;          // spins carried by the dynamics (including an ancilla)

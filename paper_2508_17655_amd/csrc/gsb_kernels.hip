@@ -87,6 +87,9 @@ __device__ __forceinline__ bool group_sync(unsigned* ctr, unsigned target, int l
 //   BF16  : 4096 B per plane = [sub 4][lane 64][8 bf16]; kk = 32*sub + 8*(lane/16) + e
 //   FP32  : 8192 B = [grp 8][lane 64][4 f32];  kk = 16*grp + 4*(lane/16) + t, where
 //           element t feeds the t-th of four 16x16x4 MFMAs of that group.
+//   FIX16 : 2048 B per plane = [half 2][lane 64][16 x int8]; kk = 64*half + 16*(lane/16) + b
+//           (16x16x64 int8 MFMA); plane 0 holds hi, plane 1 lo of q = rint(x 2^14) =
+//           256 hi + lo, hi in [-64, 64], lo in [-128, 127].
 // (kk = k mod 128.)  J uses the same layouts with the row i in place of the replica r.
 // ---------------------------------------------------------------------------------------
 template <int FORM, bool DISC>
@@ -128,6 +131,21 @@ __device__ __forceinline__ void store_operand(uint8_t* qbuf, size_t plane_bytes,
     v2u wl{(unsigned)lo[0] | ((unsigned)lo[1] << 16), (unsigned)lo[2] | ((unsigned)lo[3] << 16)};
     *reinterpret_cast<v2u*>(qbuf + off) = wh;
     *reinterpret_cast<v2u*>(qbuf + plane_bytes + off) = wl;
+  } else if constexpr (FORM == kFormFIX16) {
+    unsigned wh = 0, wl = 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float q = discrete ? (xv[v] < 0.0f ? -1.0f : 1.0f) : xv[v];
+      const int qi = (int)__builtin_rintf(q * 16384.0f);  // exact scaling, round half to even
+      const int hi = (qi + 128) >> 8;
+      const int lo = qi - 256 * hi;
+      wh |= (unsigned)(hi & 0xFF) << (8 * v);
+      wl |= (unsigned)(lo & 0xFF) << (8 * v);
+    }
+    const int lanep = (lane & 15) + 16 * ((kk0 & 63) >> 4);
+    const size_t off = ((size_t)(rb * nks + kc) * 2 + (kk0 >> 6)) * 1024 + lanep * 16 + (kk0 & 15);
+    *reinterpret_cast<unsigned*>(qbuf + off) = wh;
+    *reinterpret_cast<unsigned*>(qbuf + plane_bytes + off) = wl;
   } else {
     v4f q;
 #pragma unroll
@@ -350,6 +368,48 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
           }
         }
       }
+    } else if constexpr (FORM == kFormFIX16) {
+      // two int8 passes (hi, lo planes; the sign operand has lo = 0), exact int32 sums;
+      // G = 256 G_hi + G_lo is exact in int32 and rounded to binary32 once, then scaled
+      constexpr int planes = DISC ? 1 : 2;
+      v4i iacc[2][4][2];
+#pragma unroll
+      for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) iacc[pl][rt][ct] = v4i{0, 0, 0, 0};
+      for (int ks = 0; ks < nks; ++ks) {
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+          v4i aj[4];
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt)
+            aj[rt] = *reinterpret_cast<const v4i*>(jrows + ((size_t)(rt * nks + ks) * 2 + half) * 1024 + lane * 16);
+#pragma unroll
+          for (int pl = 0; pl < planes; ++pl) {
+            v4i bq[2];
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) {
+              const unsigned base =
+                  (unsigned)(pl * plane_bytes + ((size_t)((rb0 + ct) * nks + ks) * 2 + half) * 1024 + lane * 16);
+              bq[ct] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kPolicySc1));
+            }
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+              for (int ct = 0; ct < 2; ++ct)
+                iacc[pl][rt][ct] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aj[rt], bq[ct], iacc[pl][rt][ct], 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            acc[rt][ct][v] = (float)(iacc[0][rt][ct][v] * 256 + iacc[1][rt][ct][v]) * 0x1p-14f;
     } else {  // FP32
       gemm_tile_fp32(jrows, qr, rb0, nks, lane, acc);
     }
@@ -887,6 +947,10 @@ __global__ void k_encode_j(const float* j32, int np, uint8_t* jf) {
       const int lanep = (i & 15) + 16 * (kk >> 5);
       const size_t off = ((size_t)(rt * nks + kc) * 2 + ((kk & 31) >> 4)) * 1024 + lanep * 16 + (kk & 15);
       jf[off] = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xFF);
+    } else if constexpr (FORM == kFormFIX16) {  // int8 J (entries in {0, +-1})
+      const int lanep = (i & 15) + 16 * ((kk & 63) >> 4);
+      const size_t off = ((size_t)(rt * nks + kc) * 2 + (kk >> 6)) * 1024 + lanep * 16 + (kk & 15);
+      jf[off] = (uint8_t)(int8_t)(int)v;
     } else if constexpr (FORM == kFormBF16X2) {
       const int lanep = (i & 15) + 16 * ((kk & 31) >> 3);
       const size_t off = ((size_t)(rt * nks + kc) * 4 + (kk >> 5)) * 1024 + lanep * 16 + (kk & 7) * 2;
@@ -1262,6 +1326,7 @@ const void* steps_kernel_disc(int form, int kind, int np) {
   switch (form) {
     case kFormFP8: return steps_kernel<kFormFP8, DISC>();
     case kFormBF16X2: return steps_kernel<kFormBF16X2, DISC>();
+    case kFormFIX16: return steps_kernel<kFormFIX16, DISC>();
     default: return steps_kernel<kFormFP32, DISC>();
   }
 }
@@ -1298,6 +1363,7 @@ hipError_t launch_encode_j(int form, bool fp4, const float* j32, int np, void* j
     hipLaunchKernelGGL(k_encode_j4, dim3(grid_for(total / 2, 256)), block, 0, stream, j32, np, out);
   else if (form == kFormFP8) hipLaunchKernelGGL(k_encode_j<kFormFP8>, grid, block, 0, stream, j32, np, out);
   else if (form == kFormBF16X2) hipLaunchKernelGGL(k_encode_j<kFormBF16X2>, grid, block, 0, stream, j32, np, out);
+  else if (form == kFormFIX16) hipLaunchKernelGGL(k_encode_j<kFormFIX16>, grid, block, 0, stream, j32, np, out);
   else hipLaunchKernelGGL(k_encode_j<kFormFP32>, grid, block, 0, stream, j32, np, out);
   return hipGetLastError();
 }

@@ -21,13 +21,13 @@ GSB_OK, GSB_EINVAL, GSB_ENOTSYM, GSB_EDIAG, GSB_ENONFINITE = 0, -1, -2, -3, -4
 GSB_ENOMEM, GSB_EDEVICE, GSB_ESTATE, GSB_EUNSUPPORTED = -5, -6, -7, -8
 GSB_BSB, GSB_DSB, GSB_GBSB, GSB_GDSB = 0, 1, 2, 3
 GSB_SCHED_LINEAR, GSB_SCHED_CONSTANT = 0, 1
-GSB_PREC_FP32, GSB_PREC_BF16X2, GSB_PREC_FP8 = 0, 1, 2
+GSB_PREC_FP32, GSB_PREC_BF16X2, GSB_PREC_FP8, GSB_PREC_FIX16 = 0, 1, 2, 3
 GSB_INIT_X, GSB_INIT_XY, GSB_INIT_PM01, GSB_INIT_PAIRS = 0, 1, 2, 3
 (GSB_OPT_C, GSB_OPT_PRECISION, GSB_OPT_INIT_MODE, GSB_OPT_LAMBDA_MAX, GSB_OPT_LAMBDA_MIN, GSB_OPT_N,
  GSB_OPT_STEP, GSB_OPT_REPLICAS, GSB_OPT_DT_STABLE, GSB_OPT_N_DYN) = range(10)
 
 VARIANTS = {"bsb": GSB_BSB, "dsb": GSB_DSB, "gbsb": GSB_GBSB, "gsb": GSB_GBSB, "gdsb": GSB_GDSB}
-PRECISIONS = {"fp32": GSB_PREC_FP32, "bf16x2": GSB_PREC_BF16X2, "fp8": GSB_PREC_FP8}
+PRECISIONS = {"fp32": GSB_PREC_FP32, "bf16x2": GSB_PREC_BF16X2, "fp8": GSB_PREC_FP8, "fix16": GSB_PREC_FIX16}
 
 STATUS_NAMES = {0: "GSB_OK", -1: "GSB_EINVAL", -2: "GSB_ENOTSYM", -3: "GSB_EDIAG", -4: "GSB_ENONFINITE",
                 -5: "GSB_ENOMEM", -6: "GSB_EDEVICE", -7: "GSB_ESTATE", -8: "GSB_EUNSUPPORTED"}
