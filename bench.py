@@ -43,9 +43,16 @@ def _finite(v: float):
     return v if math.isfinite(v) else None
 
 
+# sources that determine the register-resident step kernel's machine code
+RJ_SOURCES = ("gsb_steps_rj.hip", "gsb_device.h", "gsb_internal.h")
+
+
 def kernel_source_hash() -> str:
-    with open(os.path.join(ROOT, "paper_2508_17655_amd", "csrc", "gsb_kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in RJ_SOURCES:
+        with open(os.path.join(ROOT, "paper_2508_17655_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(name: str):

@@ -235,6 +235,126 @@ gsb_status gsb_vjp(gsb_ctx* ctx, int32_t count, float* xb, float* yb, float* pb)
  * Synchronises the stream. */
 gsb_status gsb_last_step_ms(gsb_ctx* ctx, double* ms);
 
+/* ---- Batched instances ---------------------------------------------------------------
+ * A batch holds `count` Ising instances of (possibly) different sizes n_k, each with J in
+ * {0, +1, -1} and no field, and runs `replicas` replicas of every instance in ONE
+ * persistent kernel launch.  This is batch processing (Sec. VI: several problems solved
+ * side by side) generalised to instances of different sizes.  Every instance computes
+ * exactly what a context in GSB_PREC_FP8 computes for it (the E4M3 product of eq. (3),
+ * or the sign product of dSB/GdSB, with the binary32 update of eqs. (3)-(7)): bit for
+ * bit the same x, y, p and energies for the same J, variant, A, c, dt, steps and seed
+ * seed + k (k = the instance index), with GSB_OPT_INIT_MODE = the batch's init mode.
+ *
+ * Placement: each replica group of an instance (a tile of 64, 128 or 256 spin rows by
+ * 8192 / rows replicas; see GSB_BATCH_TILE_ROWS) is a gang of n_p / rows workgroups
+ * that run together; gangs wait in one queue per XCD, balanced by the host (longest
+ * processing time first), and a workgroup that finishes a gang takes the next slot of
+ * its queue.  gsb_batch_autotune measures the step time of every instance at each tile
+ * shape on the device and later runs use the fastest one.
+ *
+ * Same conventions as the rest of this header; a batch is used by one host thread at a
+ * time, except gsb_batch_set_coupling, which may run on several threads at once for
+ * different instances (the eigenvalue estimates then run in parallel). */
+typedef struct gsb_batch gsb_batch; /* opaque; owns host tables and device buffers */
+
+typedef enum {
+  GSB_BATCH_C = 0,          /* per instance: c (default 1/lambda_max, App. A) */
+  GSB_BATCH_DT = 1,         /* per instance: dt (default eq. (13) with D_t = 1.25) */
+  GSB_BATCH_LAMBDA_MAX = 2, /* per instance, read-only: lambda_max (when it was computed) */
+  GSB_BATCH_LAMBDA_MIN = 3, /* per instance, read-only: lambda_min (when it was computed) */
+  GSB_BATCH_TILE_ROWS = 4,  /* per instance: 64, 128 or 256 spin rows per workgroup tile;
+                               0 (default) = automatic: the fastest measured tile, else the
+                               smallest whose gang fits in one XCD's workgroups */
+  GSB_BATCH_STEP_US = 5,    /* per instance, read-only: measured microseconds per step of one
+                               replica group at the current tile (0 = not measured) */
+  GSB_BATCH_N = 6,          /* per instance, read-only: n */
+  GSB_BATCH_GRAPH = 7,      /* batch-wide (k = -1): 1 = gsb_batch_run captures its launch
+                               sequence in a HIP graph once and replays it while the run's
+                               arguments and the batch are unchanged (default 0) */
+  GSB_BATCH_INIT_MODE = 8,  /* batch-wide (k = -1): gsb_init_mode (default GSB_INIT_X) */
+  GSB_BATCH_COUNT = 9,      /* batch-wide, read-only: count */
+  GSB_BATCH_REPLICAS = 10,  /* batch-wide, read-only: replicas */
+  GSB_BATCH_GRID = 11       /* batch-wide, read-only: workgroups of the persistent launch */
+} gsb_batch_option;
+
+/* Create a batch of `count` instances (1 <= count <= 65536) of sizes n[k]
+ * (1 <= n[k] <= 8192; host array, copied), `replicas` replicas each (1..65536).
+ * Needs no device memory yet.  Errors: EINVAL, ENOMEM. */
+gsb_status gsb_batch_create(int32_t count, const int32_t* n, int32_t replicas, gsb_batch** out);
+
+/* Release the batch (a bound workspace stays the caller's).  NULL is ignored. */
+void gsb_batch_destroy(gsb_batch* batch);
+
+/* Bind the HIP stream all device work of the batch is enqueued on (NULL: null stream). */
+gsb_status gsb_batch_set_stream(gsb_batch* batch, void* stream);
+
+/* Device memory the batch needs (all instances' J, states, operands, energies), bytes. */
+gsb_status gsb_batch_workspace_size(gsb_batch* batch, size_t* bytes);
+
+/* Bind caller-owned device memory (256-byte aligned, at least gsb_batch_workspace_size
+ * bytes) before the first gsb_batch_set_coupling; otherwise the library allocates it
+ * there.  Errors: EINVAL, ENOMEM (too small), ESTATE (couplings already set). */
+gsb_status gsb_batch_bind_workspace(gsb_batch* batch, void* device_ptr, size_t bytes);
+
+/* Give instance k its coupling matrix and parameters.
+ *   J  : host, n_k * n_k binary32, row-major, entries in {0, +1, -1}, exactly symmetric,
+ *        zero diagonal (eq. (1)).  Uploaded (as FP4 in the fragment layout of the FP8
+ *        product) before the call returns.
+ *   c  : > 0, or <= 0 for c = 1/lambda_max (App. A).
+ *   dt : > 0, or <= 0 for eq. (13), dt = 1.25 sqrt(2 / (1 - lambda_min / lambda_max)).
+ * lambda_max and lambda_min are estimated on the host (Lanczos, binary64) only when c or
+ * dt is left to the library.  Synchronises the stream.
+ * Errors: EINVAL, EDIAG, ENOTSYM, ENONFINITE, EUNSUPPORTED (entries outside {0, +-1}),
+ * ENOMEM, EDEVICE. */
+gsb_status gsb_batch_set_coupling(gsb_batch* batch, int32_t k, const float* J, double c, double dt);
+
+/* Set / read an option (gsb_batch_option) of instance k, or of the batch with k = -1.
+ * Errors: EINVAL (unknown option, bad value or index), ESTATE (no coupling yet / value
+ * not computed), EDEVICE. */
+gsb_status gsb_batch_set(gsb_batch* batch, int32_t k, int32_t option, double value);
+gsb_status gsb_batch_get(gsb_batch* batch, int32_t k, int32_t option, double* value);
+
+/* Measure, on the device, the step time of every instance at each tile shape (64, 128
+ * and 256 rows; shapes whose gang does not fit in one XCD are skipped) with trial runs of
+ * `trial_steps` steps of the whole batch, and keep the results for later runs (tile
+ * choice and queue balance).  Instances with a fixed GSB_BATCH_TILE_ROWS keep it.
+ * Leaves no current run.  Synchronises.  Errors: EINVAL, ESTATE, EUNSUPPORTED, EDEVICE. */
+gsb_status gsb_batch_autotune(gsb_batch* batch, int32_t variant, double control_strength, int32_t trial_steps,
+                              uint64_t seed);
+
+/* Run every instance: starting states (instance k from seed + k), M = `steps` steps of
+ * `variant` with control strength A (ignored for bSB and dSB) in one persistent launch,
+ * then the energies and best replica of every instance.  Asynchronous on the stream.
+ * Errors: EINVAL, ESTATE (an instance without coupling), EUNSUPPORTED (an instance too
+ * large for one XCD's workgroups), ENOMEM, EDEVICE. */
+gsb_status gsb_batch_run(gsb_batch* batch, int32_t variant, double control_strength, int32_t steps, uint64_t seed);
+
+/* Energies, eq. (1), of the `replicas` replicas of instance k after the last run
+ * (exact; host, `replicas` doubles).  Synchronises.  Errors: EINVAL, ESTATE, EDEVICE. */
+gsb_status gsb_batch_energy(gsb_batch* batch, int32_t k, double* energies);
+
+/* Lowest energy and its replica (ties to the lowest index) of every instance after the
+ * last run; host arrays of `count` entries, either may be NULL.  Synchronises. */
+gsb_status gsb_batch_best(gsb_batch* batch, double* energy, int32_t* replica);
+
+/* State of instance k after the last run: x, y, p host arrays of replicas * n_k binary32
+ * (replica-major), any may be NULL.  Synchronises. */
+gsb_status gsb_batch_state(gsb_batch* batch, int32_t k, float* x, float* y, float* p);
+
+/* Device time of the last gsb_batch_run in milliseconds (HIP events on the stream): the
+ * persistent step kernel alone, or, with GSB_BATCH_GRAPH, the whole graph (starting
+ * states, steps, energies).  Synchronises the stream. */
+gsb_status gsb_batch_last_ms(gsb_batch* batch, double* ms);
+
+/* The queue plan gsb_batch_run uses, for inspection: `units` units (here: instances),
+ * unit u being gangs[u] gangs of width[u] workgroups that take cost[u] each, over
+ * `queues` queues of `workers` workgroups.  Longest processing time first: units in
+ * decreasing order of gangs * width * cost, each to the queue with the least work so
+ * far; queue[u] receives the queue and rank[u] the position within it (decreasing cost,
+ * then width, then index).  Host only.  Errors: EINVAL, EUNSUPPORTED (width > workers). */
+gsb_status gsb_batch_plan(int32_t units, const int32_t* width, const int32_t* gangs, const double* cost,
+                          int32_t queues, int32_t workers, int32_t* queue, int32_t* rank);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* gsb_last_error(void);
 

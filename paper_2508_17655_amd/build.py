@@ -22,7 +22,8 @@ DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-f
 def build(verbose: bool = False) -> str:
     objs = []
     common = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-result"]
-    for src, extra in (("gsb_kernels.hip", DEVICE_FLAGS), ("gsb_api.cpp", ["-ffp-contract=off"])):
+    for src, extra in (("gsb_kernels.hip", DEVICE_FLAGS), ("gsb_steps_rj.hip", DEVICE_FLAGS),
+                       ("gsb_api.cpp", ["-ffp-contract=off"]), ("gsb_batch.cpp", ["-ffp-contract=off"])):
         obj = os.path.join(CSRC, src + ".o")
         cmd = [HIPCC, *common, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):

@@ -79,8 +79,31 @@ double tridiag_eig(const std::vector<double>& a, const std::vector<double>& b, i
   return 0.5 * (lo + hi);
 }
 
-void extreme_eigenvalues(const std::vector<float>& J, int n, double* lmax, double* lmin) {
+}  // namespace
+
+void gsb::set_last_error(const char* msg) { g_err = msg; }
+
+void gsb::extreme_eigenvalues(const float* J, int n, double* lmax, double* lmin) {
   if (n == 1) { *lmax = 0.0; *lmin = 0.0; return; }
+  // a sparse J (at most a quarter of the entries nonzero) is multiplied in compressed rows
+  size_t nnz = 0;
+  for (size_t k = 0; k < (size_t)n * n; ++k) nnz += J[k] != 0.0f;
+  const bool sparse = nnz * 4 <= (size_t)n * n;
+  std::vector<size_t> row_ptr;
+  std::vector<int> col;
+  std::vector<float> val;
+  if (sparse) {
+    row_ptr.assign(n + 1, 0);
+    col.reserve(nnz);
+    val.reserve(nnz);
+    for (int i = 0; i < n; ++i) {
+      for (int j = 0; j < n; ++j) {
+        const float v = J[(size_t)i * n + j];
+        if (v != 0.0f) { col.push_back(j); val.push_back(v); }
+      }
+      row_ptr[i + 1] = col.size();
+    }
+  }
   const int kmax = std::min(n, 400);
   std::vector<std::vector<double>> V;
   std::vector<double> alpha, beta;
@@ -103,8 +126,12 @@ void extreme_eigenvalues(const std::vector<float>& J, int n, double* lmax, doubl
     V.push_back(v);
     for (int i = 0; i < n; ++i) {
       double acc = 0;
-      const float* Ji = &J[(size_t)i * n];
-      for (int j = 0; j < n; ++j) acc += (double)Ji[j] * v[j];
+      if (sparse) {
+        for (size_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) acc += (double)val[e] * v[col[e]];
+      } else {
+        const float* Ji = J + (size_t)i * n;
+        for (int j = 0; j < n; ++j) acc += (double)Ji[j] * v[j];
+      }
       w[i] = acc;
     }
     double a = 0;
@@ -139,8 +166,6 @@ void extreme_eigenvalues(const std::vector<float>& J, int n, double* lmax, doubl
   *lmax = prev_max;
   *lmin = prev_min;
 }
-
-}  // namespace
 
 struct gsb_ctx {
   // instance
@@ -291,7 +316,7 @@ gsb_status ensure_workspace(gsb_ctx* c, size_t need) {
 
 gsb_status ensure_eig(gsb_ctx* c) {
   if (!c->eig_done) {
-    extreme_eigenvalues(c->J, c->n, &c->lmax, &c->lmin);
+    extreme_eigenvalues(c->J.data(), c->n, &c->lmax, &c->lmin);
     c->eig_done = true;
   }
   return GSB_OK;
@@ -511,7 +536,7 @@ gsb_status carve_and_prepare(gsb_ctx* c, const Layout& L, int kind, int form, in
     c->j32_ready = true;
     c->jf_form = -1;
   }
-  const bool j_fp4 = kind != kKindGeneric;  // the FP8 kinds with J on chip keep J as FP4
+  const bool j_fp4 = form == kFormFP8;  // the FP8 product reads J as FP4 (exact for 0, +-1)
   const int jcode = form * 2 + (j_fp4 ? 1 : 0);
   if (c->jf_form != jcode) {
     HIP_TRY(launch_encode_j(form, j_fp4, c->j32, c->np, c->jf, c->stream), "encode J");

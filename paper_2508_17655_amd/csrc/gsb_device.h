@@ -1,0 +1,163 @@
+// gsb_device.h -- device code shared by the step kernels of libgsb (gfx950): vector
+// types, buffer resources, the replica-group barrier and the fragment-major operand
+// encodings.  Included by the kernel translation units only.
+#pragma once
+#include "gsb_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace gsb {
+namespace {
+
+
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int kPolicySc1 = 16;             // buffer-load cache policy: device scope (skips L1)
+constexpr unsigned kSpinLimit = 1u << 22;  // polls before a barrier gives up (seconds)
+constexpr int kHwRegXccId = 20 | (0 << 6) | ((4 - 1) << 11);  // hwreg(HW_REG_XCC_ID, 0, 4)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ v8i cat(v4i a, v4i b) {
+  return v8i{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+}
+
+__device__ __forceinline__ unsigned ld_dev(const unsigned* p) {
+  return __hip_atomic_load(const_cast<unsigned*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(unsigned* p, unsigned v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Barrier over the `nb` workgroups that share a replica group.  Every wave first waits
+// until its own stores are acknowledged (they are then in L2), then one thread counts
+// the workgroup in and polls the counter with device-scope loads.  When all members sit
+// on one XCD (`local`) they share that XCD's L2, and operand loads that skip L1 see the
+// data without any cache maintenance; otherwise the agent-scope release/acquire fences
+// write back and invalidate the caches between XCDs.
+__device__ __forceinline__ bool group_sync(unsigned* ctr, unsigned target, int local,
+                                           unsigned* abort_flag, unsigned* status, int* s_flag) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (!local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    unsigned spins = 0;
+    while (ld_dev(ctr) < target) {
+      ++spins;
+      if ((spins & 63u) == 0 && ld_dev(abort_flag)) { ok = 0; break; }
+      if (spins > kSpinLimit) { st_dev(abort_flag, 1u); st_dev(status, 1u); ok = 0; break; }
+    }
+    if (!local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *s_flag = ok;
+  }
+  __syncthreads();
+  return *s_flag != 0;
+}
+
+// ---------------------------------------------------------------------------------------
+// Operand encodings and their fragment-major placement.
+//
+// Q holds, per (16-replica block rb, 128-spin k-step kc), the operand bytes in exactly the
+// order the MFMA B operand is held in a wavefront's lanes, so a fragment is one coalesced
+// 1 KiB load per VGPR quad:
+//   FP8   : 2048 B = [half 2][lane 64][16 B];  lane = r%16 + 16*(kk/32),
+//           byte 16*half + b  <->  kk = 32*(lane/16) + 16*half + b            (16x16x128)
+//   BF16  : 4096 B per plane = [sub 4][lane 64][8 bf16]; kk = 32*sub + 8*(lane/16) + e
+//   FP32  : 8192 B = [grp 8][lane 64][4 f32];  kk = 16*grp + 4*(lane/16) + t, where
+//           element t feeds the t-th of four 16x16x4 MFMAs of that group.
+//   FIX16 : 2048 B per plane = [half 2][lane 64][16 x int8]; kk = 64*half + 16*(lane/16) + b
+//           (16x16x64 int8 MFMA); plane 0 holds hi, plane 1 lo of q = rint(x 2^14) =
+//           256 hi + lo, hi in [-64, 64], lo in [-128, 127].
+// (kk = k mod 128.)  J uses the same layouts with the row i in place of the replica r.
+// ---------------------------------------------------------------------------------------
+template <int FORM, bool DISC>
+__device__ __forceinline__ void store_operand(uint8_t* qbuf, size_t plane_bytes, int nks,
+                                              int ibase, int rcol, int lane, const float xv[4]) {
+  constexpr bool discrete = DISC;
+  const int rb = rcol >> 4;
+  const int kc = ibase >> 7;
+  const int kk0 = (ibase & 127) + 4 * (lane >> 4);  // first of this lane's 4 rows
+  if constexpr (FORM == kFormFP8) {
+    unsigned w;
+    if constexpr (discrete) {
+      w = 0x38383838u;  // +1.0 in E4M3 in every byte
+      w |= (xv[0] < 0.0f ? 0x80u : 0u) | (xv[1] < 0.0f ? 0x8000u : 0u) |
+           (xv[2] < 0.0f ? 0x800000u : 0u) | (xv[3] < 0.0f ? 0x80000000u : 0u);
+    } else {
+      int lo = __builtin_amdgcn_cvt_pk_fp8_f32(xv[0], xv[1], 0, false);
+      w = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(xv[2], xv[3], lo, true);
+    }
+    const int lanep = (lane & 15) + 16 * (kk0 >> 5);
+    const int half = (kk0 & 31) >> 4;
+    const size_t off = ((size_t)(rb * nks + kc) * 2 + half) * 1024 + lanep * 16 + (kk0 & 15);
+    *reinterpret_cast<unsigned*>(qbuf + off) = w;
+  } else if constexpr (FORM == kFormBF16X2) {
+    unsigned short hi[4], lo[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float q = discrete ? (xv[v] < 0.0f ? -1.0f : 1.0f) : xv[v];
+      __bf16 h = (__bf16)q;
+      float hf = (float)h;
+      __bf16 l = (__bf16)(q - hf);  // q - hf is exact in binary32
+      hi[v] = __builtin_bit_cast(unsigned short, h);
+      lo[v] = __builtin_bit_cast(unsigned short, l);
+    }
+    const int sub = kk0 >> 5;
+    const int lanep = (lane & 15) + 16 * ((kk0 & 31) >> 3);
+    const size_t off = ((size_t)(rb * nks + kc) * 4 + sub) * 1024 + lanep * 16 + (kk0 & 7) * 2;
+    v2u wh{(unsigned)hi[0] | ((unsigned)hi[1] << 16), (unsigned)hi[2] | ((unsigned)hi[3] << 16)};
+    v2u wl{(unsigned)lo[0] | ((unsigned)lo[1] << 16), (unsigned)lo[2] | ((unsigned)lo[3] << 16)};
+    *reinterpret_cast<v2u*>(qbuf + off) = wh;
+    *reinterpret_cast<v2u*>(qbuf + plane_bytes + off) = wl;
+  } else if constexpr (FORM == kFormFIX16) {
+    unsigned wh = 0, wl = 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float q = discrete ? (xv[v] < 0.0f ? -1.0f : 1.0f) : xv[v];
+      const int qi = (int)__builtin_rintf(q * 16384.0f);  // exact scaling, round half to even
+      const int hi = (qi + 128) >> 8;
+      const int lo = qi - 256 * hi;
+      wh |= (unsigned)(hi & 0xFF) << (8 * v);
+      wl |= (unsigned)(lo & 0xFF) << (8 * v);
+    }
+    const int lanep = (lane & 15) + 16 * ((kk0 & 63) >> 4);
+    const size_t off = ((size_t)(rb * nks + kc) * 2 + (kk0 >> 6)) * 1024 + lanep * 16 + (kk0 & 15);
+    *reinterpret_cast<unsigned*>(qbuf + off) = wh;
+    *reinterpret_cast<unsigned*>(qbuf + plane_bytes + off) = wl;
+  } else {
+    v4f q;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) q[v] = discrete ? (xv[v] < 0.0f ? -1.0f : 1.0f) : xv[v];
+    const int grp = kk0 >> 4;
+    const int lanep = (lane & 15) + 16 * ((kk0 & 15) >> 2);
+    const size_t off = ((size_t)(rb * nks + kc) * 8 + grp) * 1024 + lanep * 16;
+    *reinterpret_cast<v4f*>(qbuf + off) = q;
+  }
+}
+
+// J (zero padded, entries in {0, +-1}) -> FP4 (E2M1) fragment-major layout of the
+// register-resident FP8 path: [row tile][k-step][lane 64][16 bytes], two values per byte,
+// low nibble first.  In the mixed FP4 x FP8 MFMA (16x16x128), FP8 byte j of lane group g
+// multiplies FP4 nibble p of the same row/column lanes with p = 16 g + j for j < 16 and
+// p = 64 + 16 g + (j - 16) for j >= 16 (p counts nibbles over the four lane groups,
+// 32 per group).  The FP8 operand layout puts k-step offset kk = 32 g + j at byte j of
+// lane group g, so nibble p must hold kk(p) below.
+__device__ __forceinline__ int fp4_pair_kk(int p) {
+  return p < 64 ? 32 * (p >> 4) + (p & 15) : 32 * ((p - 64) >> 4) + 16 + ((p - 64) & 15);
+}
+__device__ __forceinline__ unsigned fp4_code(float v) {  // exact for 0 and +-1
+  return (v < 0.0f ? 0x8u : 0u) | (__builtin_fabsf(v) == 1.0f ? 0x2u : 0u);
+}
+
+}  // namespace
+}  // namespace gsb

@@ -1,5 +1,5 @@
-// Internal interface between the C ABI (gsb_api.cpp) and the gfx950 kernels
-// (gsb_kernels.hip).  Not installed; not part of the public ABI.
+// Internal interface between the C ABI (gsb_api.cpp, gsb_batch.cpp) and the gfx950
+// kernels (gsb_kernels.hip, gsb_steps_rj.hip).  Not installed; not part of the public ABI.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
@@ -7,9 +7,8 @@
 
 namespace gsb {
 
-// Tile geometry of the persistent step kernel: one workgroup of 4 waves per tile, each
-// wave a 64-spin x 32-replica tile.  With J resident in LDS (FP8 product, J stored as
-// FP4) a workgroup is 128 spins x 64 replicas; otherwise 64 spins x 128 replicas.
+// Tile geometry of the persistent step kernels: one workgroup of 4 waves per tile, each
+// wave a 64-spin x 32-replica tile (see Kind for the workgroup shapes).
 constexpr int kWaveRows = 64;
 constexpr int kWaveCols = 32;
 constexpr int kRepPad = 128;   // replica counts are padded to a multiple of this
@@ -25,7 +24,9 @@ enum Form { kFormFP32 = 0, kFormBF16X2 = 1, kFormFP8 = 2, kFormFIX16 = 3 };
 // Step-kernel variants.
 //   kKindRegJ : FP8 product, np <= 2048: J rows in registers (FP4), 256 spins x 32 replicas
 //               per workgroup, two half-step-offset column sub-groups.
-//   kKindGeneric : J fragments from L2 (any form), 64 spins x 128 replicas per workgroup.
+//   kKindGeneric : J fragments from L2 (any form; FP4 J for the FP8 product), 64 spins x
+//               128 replicas per workgroup (the batched kernel also runs 128 x 64 and
+//               256 x 32 tiles).
 enum Kind { kKindGeneric = 0, kKindRegJ = 2 };
 
 __host__ __device__ constexpr int tile_rows_kind(int kind) { return kind == kKindRegJ ? 256 : 64; }
@@ -65,6 +66,33 @@ struct StepArgs {
 
 inline size_t sync_words(int groups) { return (size_t)(4 * groups + 1) * 64; }
 
+// ---- batched instances (one persistent launch over many instances of different n) ----
+// Slot of a queue: workgroup mb of replica group g of instance `inst`, in tiles of `bm`
+// spin rows (64, 128 or 256) x 8192 / bm replicas.  The nb = np / bm slots of one
+// (instance, group) pair form a gang: they run together and synchronise every step.
+struct BatchSlot { int inst, g, mb, bm; };
+// Per-instance buffers beside the instance's StepArgs (FP8 product; a.jf is FP4 J).
+struct BatchInst {
+  uint64_t seed;    // initial state: the single-instance generator with this seed
+  uint8_t* s8;      // sign operand of the energy product, rp x np bytes
+  int* eacc;        // integer energy sums, rp ints (zeroed before the energy kernels)
+  double* E;        // energies, rp doubles
+  int* best_idx;    // lowest-energy replica (ties to the lowest index)
+  double* best_e;
+};
+constexpr int kBatchXcds = 8;        // per-XCD queues 0..7; queue 8 spans the device
+constexpr int kBatchCtlWords = 256;  // control words of a batched launch (zeroed before it)
+struct BatchArgs {
+  const StepArgs* inst;       // per-instance step arguments (device array)
+  const BatchSlot* slots;     // queue d holds slots [qoff[d], qoff[d + 1]), d = 0..8
+  const int* qoff;            // kBatchXcds + 2 offsets
+  const int* need;            // per XCD queue: workgroups its widest gang needs
+  unsigned* ctl;              // kBatchCtlWords words, zero at launch
+  unsigned* status;           // 1: a gang barrier timed out; 2: the start-up count did
+  unsigned long long* clk;    // per slot: wall-clock ticks at start and end, or nullptr
+  int grid;                   // workgroups of the launch (all co-resident)
+};
+
 // ---- launchers (all asynchronous on `stream`) ----
 hipError_t launch_fill_u32(unsigned* p, size_t count, unsigned v, hipStream_t stream);
 hipError_t launch_encode_j(int form, bool fp4, const float* j32, int np, void* jf, hipStream_t stream);
@@ -75,6 +103,8 @@ hipError_t launch_init_state(int n, int np, int rp, uint64_t seed, int mode, flo
 // blocks of 32 = 16 replicas followed by their 16 tangents.
 hipError_t launch_steps(int form, int kind, const StepArgs& a, hipStream_t stream, bool tangent = false);
 int max_coresident_workgroups(int form, int kind, int np, bool tangent = false);
+// The register-resident FP8 kernel for nks = np / 128 in {4, 8, 12, 16}, else nullptr.
+const void* steps_kernel_rj(int nks, bool discrete);
 // Reverse pass of the binary32 dynamics over a recorded tape (see k_adjoint); a.x, a.y,
 // a.p carry the cotangents in and out.  Occupancy limit of that kernel.
 hipError_t launch_adjoint(const StepArgs& a, hipStream_t stream);
@@ -105,5 +135,20 @@ hipError_t launch_best(const double* energies, int r_count, int* best_idx, doubl
                        hipStream_t stream);
 hipError_t launch_spins(const float* x, int n_out, int np, int r_first, int r_count, int anc,
                         const int* r_index, int8_t* spins, hipStream_t stream);
+
+// Batched instances (FP8 product, variants by `discrete`): the persistent queue kernel,
+// its co-resident workgroups per CU, and the per-instance start, energy and best kernels
+// over `count` instances (np_max: the largest np; rp replicas each, r_count of them real).
+hipError_t launch_steps_batch(bool discrete, const BatchArgs& b, hipStream_t stream, bool cooperative);
+int batch_workgroups_per_cu(bool discrete);
+hipError_t launch_init_batch(const StepArgs* inst, const BatchInst* bi, int count, int np_max, int rp, int mode,
+                             hipStream_t stream);
+hipError_t launch_energy_batch(const StepArgs* inst, const BatchInst* bi, int count, int np_max, int rp,
+                               int r_count, hipStream_t stream);
+// Message of the last failed C ABI call on this thread (read by gsb_last_error).
+void set_last_error(const char* msg);
+// Lanczos estimate of the extreme eigenvalues of the symmetric n x n matrix J (host,
+// binary64; a sparse J is multiplied in compressed-row form).
+void extreme_eigenvalues(const float* J, int n, double* lmax, double* lmin);
 
 }  // namespace gsb

@@ -12,7 +12,7 @@
 // Floating-point contraction is disabled for this file: the update is evaluated as one
 // binary32 operation per arithmetic operator, in the order written, so the sign and E4M3
 // forms reproduce a strict binary32 evaluation bit for bit.
-#include "gsb_internal.h"
+#include "gsb_device.h"
 
 #include <algorithm>
 
@@ -20,142 +20,6 @@
 
 namespace gsb {
 namespace {
-
-typedef int v8i __attribute__((ext_vector_type(8)));
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef unsigned v4u __attribute__((ext_vector_type(4)));
-typedef unsigned v2u __attribute__((ext_vector_type(2)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
-
-constexpr int kPolicySc1 = 16;             // buffer-load cache policy: device scope (skips L1)
-constexpr int kAccKSteps = 14;             // k_steps_rj: k-steps of J held in AGPRs (the rest in VGPRs)
-constexpr unsigned kSpinLimit = 1u << 22;  // polls before a barrier gives up (seconds)
-constexpr int kHwRegXccId = 20 | (0 << 6) | ((4 - 1) << 11);  // hwreg(HW_REG_XCC_ID, 0, 4)
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, size_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
-}
-
-__device__ __forceinline__ v8i cat(v4i a, v4i b) {
-  return v8i{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
-}
-
-__device__ __forceinline__ unsigned ld_dev(const unsigned* p) {
-  return __hip_atomic_load(const_cast<unsigned*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_dev(unsigned* p, unsigned v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Barrier over the `nb` workgroups that share a replica group.  Every wave first waits
-// until its own stores are acknowledged (they are then in L2), then one thread counts
-// the workgroup in and polls the counter with device-scope loads.  When all members sit
-// on one XCD (`local`) they share that XCD's L2, and operand loads that skip L1 see the
-// data without any cache maintenance; otherwise the agent-scope release/acquire fences
-// write back and invalidate the caches between XCDs.
-__device__ __forceinline__ bool group_sync(unsigned* ctr, unsigned target, int local,
-                                           unsigned* abort_flag, unsigned* status, int* s_flag) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (!local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int ok = 1;
-    unsigned spins = 0;
-    while (ld_dev(ctr) < target) {
-      ++spins;
-      if ((spins & 63u) == 0 && ld_dev(abort_flag)) { ok = 0; break; }
-      if (spins > kSpinLimit) { st_dev(abort_flag, 1u); st_dev(status, 1u); ok = 0; break; }
-    }
-    if (!local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    *s_flag = ok;
-  }
-  __syncthreads();
-  return *s_flag != 0;
-}
-
-// ---------------------------------------------------------------------------------------
-// Operand encodings and their fragment-major placement.
-//
-// Q holds, per (16-replica block rb, 128-spin k-step kc), the operand bytes in exactly the
-// order the MFMA B operand is held in a wavefront's lanes, so a fragment is one coalesced
-// 1 KiB load per VGPR quad:
-//   FP8   : 2048 B = [half 2][lane 64][16 B];  lane = r%16 + 16*(kk/32),
-//           byte 16*half + b  <->  kk = 32*(lane/16) + 16*half + b            (16x16x128)
-//   BF16  : 4096 B per plane = [sub 4][lane 64][8 bf16]; kk = 32*sub + 8*(lane/16) + e
-//   FP32  : 8192 B = [grp 8][lane 64][4 f32];  kk = 16*grp + 4*(lane/16) + t, where
-//           element t feeds the t-th of four 16x16x4 MFMAs of that group.
-//   FIX16 : 2048 B per plane = [half 2][lane 64][16 x int8]; kk = 64*half + 16*(lane/16) + b
-//           (16x16x64 int8 MFMA); plane 0 holds hi, plane 1 lo of q = rint(x 2^14) =
-//           256 hi + lo, hi in [-64, 64], lo in [-128, 127].
-// (kk = k mod 128.)  J uses the same layouts with the row i in place of the replica r.
-// ---------------------------------------------------------------------------------------
-template <int FORM, bool DISC>
-__device__ __forceinline__ void store_operand(uint8_t* qbuf, size_t plane_bytes, int nks,
-                                              int ibase, int rcol, int lane, const float xv[4]) {
-  constexpr bool discrete = DISC;
-  const int rb = rcol >> 4;
-  const int kc = ibase >> 7;
-  const int kk0 = (ibase & 127) + 4 * (lane >> 4);  // first of this lane's 4 rows
-  if constexpr (FORM == kFormFP8) {
-    unsigned w;
-    if constexpr (discrete) {
-      w = 0x38383838u;  // +1.0 in E4M3 in every byte
-      w |= (xv[0] < 0.0f ? 0x80u : 0u) | (xv[1] < 0.0f ? 0x8000u : 0u) |
-           (xv[2] < 0.0f ? 0x800000u : 0u) | (xv[3] < 0.0f ? 0x80000000u : 0u);
-    } else {
-      int lo = __builtin_amdgcn_cvt_pk_fp8_f32(xv[0], xv[1], 0, false);
-      w = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(xv[2], xv[3], lo, true);
-    }
-    const int lanep = (lane & 15) + 16 * (kk0 >> 5);
-    const int half = (kk0 & 31) >> 4;
-    const size_t off = ((size_t)(rb * nks + kc) * 2 + half) * 1024 + lanep * 16 + (kk0 & 15);
-    *reinterpret_cast<unsigned*>(qbuf + off) = w;
-  } else if constexpr (FORM == kFormBF16X2) {
-    unsigned short hi[4], lo[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      float q = discrete ? (xv[v] < 0.0f ? -1.0f : 1.0f) : xv[v];
-      __bf16 h = (__bf16)q;
-      float hf = (float)h;
-      __bf16 l = (__bf16)(q - hf);  // q - hf is exact in binary32
-      hi[v] = __builtin_bit_cast(unsigned short, h);
-      lo[v] = __builtin_bit_cast(unsigned short, l);
-    }
-    const int sub = kk0 >> 5;
-    const int lanep = (lane & 15) + 16 * ((kk0 & 31) >> 3);
-    const size_t off = ((size_t)(rb * nks + kc) * 4 + sub) * 1024 + lanep * 16 + (kk0 & 7) * 2;
-    v2u wh{(unsigned)hi[0] | ((unsigned)hi[1] << 16), (unsigned)hi[2] | ((unsigned)hi[3] << 16)};
-    v2u wl{(unsigned)lo[0] | ((unsigned)lo[1] << 16), (unsigned)lo[2] | ((unsigned)lo[3] << 16)};
-    *reinterpret_cast<v2u*>(qbuf + off) = wh;
-    *reinterpret_cast<v2u*>(qbuf + plane_bytes + off) = wl;
-  } else if constexpr (FORM == kFormFIX16) {
-    unsigned wh = 0, wl = 0;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const float q = discrete ? (xv[v] < 0.0f ? -1.0f : 1.0f) : xv[v];
-      const int qi = (int)__builtin_rintf(q * 16384.0f);  // exact scaling, round half to even
-      const int hi = (qi + 128) >> 8;
-      const int lo = qi - 256 * hi;
-      wh |= (unsigned)(hi & 0xFF) << (8 * v);
-      wl |= (unsigned)(lo & 0xFF) << (8 * v);
-    }
-    const int lanep = (lane & 15) + 16 * ((kk0 & 63) >> 4);
-    const size_t off = ((size_t)(rb * nks + kc) * 2 + (kk0 >> 6)) * 1024 + lanep * 16 + (kk0 & 15);
-    *reinterpret_cast<unsigned*>(qbuf + off) = wh;
-    *reinterpret_cast<unsigned*>(qbuf + plane_bytes + off) = wl;
-  } else {
-    v4f q;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) q[v] = discrete ? (xv[v] < 0.0f ? -1.0f : 1.0f) : xv[v];
-    const int grp = kk0 >> 4;
-    const int lanep = (lane & 15) + 16 * ((kk0 & 15) >> 2);
-    const size_t off = ((size_t)(rb * nks + kc) * 8 + grp) * 1024 + lanep * 16;
-    *reinterpret_cast<v4f*>(qbuf + off) = q;
-  }
-}
 
 // One wave's 64 x 32 tile of G = J Q in the binary32 form: 4 row tiles (J rows, `jrows`)
 // x 2 column tiles (Q blocks rb0, rb0 + 1 of the buffer behind `qr`) of 16x16x4 MFMAs.
@@ -186,12 +50,16 @@ __device__ __forceinline__ void gemm_tile_fp32(const uint8_t* jrows, __amdgpu_bu
 }
 
 // ---------------------------------------------------------------------------------------
-// Generic persistent step kernel (any product form; J fragments read from L2).
-// Workgroup (g, mb) owns spins [64 mb, 64 mb + 64) of replicas [128 g, 128 g + 128); each
-// of its 4 waves computes a 64 x 32 tile of G = J Q (4 x 2 MFMA tiles of 16 x 16) and
-// keeps x, y, p of those 2048 elements in registers for the whole launch.  Workgroup b
-// is (g, mb) = (b mod groups, b div groups): with 8 or 16 groups, round-robin dispatch
-// puts each group on one XCD.
+// Generic persistent step tile (any product form; J fragments read from L2 or MALL).
+// Workgroup (g, mb) owns spins [BM mb, BM mb + BM) of replicas [BN g, BN g + BN), with
+// BM x BN = 64 x 128, 128 x 64 or 256 x 32; each of its 4 waves computes a 64 x 32 tile
+// of G = J Q (4 x 2 MFMA tiles of 16 x 16) and keeps x, y, p of those 2048 elements in
+// registers for the whole launch.  The nb = np / BM workgroups of one replica group
+// synchronise every step.  For the FP8 product J is read as FP4 (E2M1, exact for 0 and
+// +-1; the FP8 form requires J in {0, +-1}), half the bytes of FP8.
+//
+// k_steps runs one tile per workgroup, b = (g, mb) = (b mod groups, b div groups): with
+// 8 or 16 groups, round-robin dispatch puts each group on one XCD.
 //
 // TANG (binary32 product, continuous variants): the launch's columns come in blocks of
 // 32 whose first 16 are replicas and whose last 16 carry the forward derivative (the
@@ -200,19 +68,15 @@ __device__ __forceinline__ void gemm_tile_fp32(const uint8_t* jrows, __amdgpu_bu
 // eqs. (7), (3), (4), (5) (see the update below); the control strength may differ per
 // replica (a.acol).
 // ---------------------------------------------------------------------------------------
-template <int FORM, bool DISC, bool TANG = false>
-__global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
+template <int FORM, bool DISC, bool TANG, int BM>
+__device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int& s_flag, int& s_local) {
   static_assert(!TANG || (FORM == kFormFP32 && !DISC), "the tangent needs the continuous binary32 product");
-  __shared__ int s_flag;
-  __shared__ int s_local;
-  constexpr int BM = tile_rows_kind(kKindGeneric);
-  constexpr int BN = tile_cols_kind(kKindGeneric);
+  static_assert(BM == 64 || BM == 128 || BM == 256, "tile rows");
+  constexpr int BN = 8192 / BM;
   constexpr int WCOLS = BN / kWaveCols;  // waves across the replica columns
   constexpr int kQPolicy = kPolicySc1;   // each wave reads its own columns: skip L1
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int g = blockIdx.x % a.groups;
-  const int mb = blockIdx.x / a.groups;
   const int wrow = wave / WCOLS;             // 64-row slice of the workgroup's rows
   const int row0 = mb * BM + wrow * kWaveRows;
   const int col0 = g * BN + (wave % WCOLS) * kWaveCols;
@@ -221,7 +85,7 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
   unsigned* hs = a.sync + (size_t)(a.groups + g) * 64;
   unsigned* msk = a.sync + (size_t)(2 * a.groups + g) * 64;
   unsigned* abort_flag = a.sync + (size_t)(3 * a.groups) * 64;
-  const size_t jblk = operand_block_bytes(FORM);
+  const size_t jblk = FORM == kFormFP8 ? 1024 : operand_block_bytes(FORM);  // FP8 product: FP4 J
   const size_t plane_bytes = a.q_buf_bytes / operand_planes(FORM);
 
   // J rows of this wave: 4 row tiles x nks k-steps, contiguous in the layout.
@@ -290,13 +154,13 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
       for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 
     if constexpr (FORM == kFormFP8) {
-      // Software pipeline: Q fragments are fetched kPF k-steps ahead from L2 and J
-      // fragments one k-step ahead from LDS, so neither latency stalls the MFMA stream.
-      // nks is a multiple of kPF (np is padded to 512); the main loop prefetches
-      // unconditionally and the last kPF k-steps are peeled without loads.
+      // Software pipeline: Q fragments are fetched kPF k-steps ahead and FP4 J fragments
+      // one k-step ahead, so neither latency stalls the MFMA stream.  nks is a multiple
+      // of kPF (np is padded to 512); the main loop prefetches unconditionally and the
+      // last kPF k-steps are peeled without loads.
       constexpr int kPF = kKStepsUnroll;
       v8i bq[kPF][2];
-      v8i aj[2][4];
+      v4i aj[2][4];
       auto load_b = [&](int ks, v8i* dst) {
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
@@ -306,20 +170,19 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
           dst[ct] = cat(lo, hi);
         }
       };
-      auto load_a = [&](int ks, v8i* dst) {
+      auto load_a = [&](int ks, v4i* dst) {
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-          const uint8_t* pa = jrows + (size_t)(rt * nks + ks) * 2048 + lane * 16;
-          dst[rt] = cat(*reinterpret_cast<const v4i*>(pa), *reinterpret_cast<const v4i*>(pa + 1024));
-        }
+        for (int rt = 0; rt < 4; ++rt)
+          dst[rt] = *reinterpret_cast<const v4i*>(jrows + (size_t)(rt * nks + ks) * 1024 + lane * 16);
       };
-      auto mfmas = [&](const v8i* aa, const v8i* bb) {
+      auto mfmas = [&](const v4i* aa, const v8i* bb) {
+        // A: FP4 (format code 4, the upper four registers unused), B: FP8 E4M3, unit scales
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
           for (int ct = 0; ct < 2; ++ct)
-            acc[rt][ct] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(aa[rt], bb[ct], acc[rt][ct], 0, 0, 0,
-                                                                           127, 0, 127);
+            acc[rt][ct] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(cat(aa[rt], aa[rt]), bb[ct], acc[rt][ct],
+                                                                           4, 0, 0, 127, 0, 127);
       };
 #pragma unroll
       for (int u = 0; u < kPF; ++u) load_b(u, bq[u]);
@@ -519,6 +382,79 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
     }
 }
 
+template <int FORM, bool DISC, bool TANG = false>
+__global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
+  __shared__ int s_flag;
+  __shared__ int s_local;
+  steps_tile<FORM, DISC, TANG, 64>(a, (int)(blockIdx.x % a.groups), (int)(blockIdx.x / a.groups), s_flag, s_local);
+}
+
+// ---------------------------------------------------------------------------------------
+// Batched instances in one persistent launch.  Batch processing (Sec. VI) runs several
+// problems side by side; here the problems may differ in size.  Every replica group of
+// every instance is a gang of nb = np / BM workgroups that must run together and meet
+// at every step's barrier.  The gangs wait in queues: one per XCD, which the host fills
+// so that each carries about the same work, and one spanning the device.  A workgroup
+// takes the next slot of its queue (an atomic counter), runs that tile for all steps,
+// then takes the next; a gang starts when all of its slots are taken.  Slots are taken
+// in queue order and no gang waits on a later one, so a queue drains whenever each of
+// its gangs fits in the workgroups serving it.  The host sizes the XCD queues for a grid
+// spread evenly over the XCDs (round-robin dispatch); the kernel counts the workgroups
+// on each XCD at start-up and, if any queue lacks workers, every workgroup serves the
+// device-wide queue instead (whose gangs all fit in the grid).
+// ---------------------------------------------------------------------------------------
+template <bool DISC>
+__global__ void __launch_bounds__(kThreads, 1) k_steps_batch(BatchArgs b) {
+  __shared__ int s_flag;
+  __shared__ int s_local;
+  __shared__ int s_slot;
+  const int tid = threadIdx.x;
+  unsigned* workers = b.ctl + 160;  // [kBatchXcds + 1]: per XCD, then any other XCC id
+  unsigned* arrived = b.ctl + 192;
+  if (tid == 0) {
+    const unsigned xcc = (unsigned)__builtin_amdgcn_s_getreg(kHwRegXccId) & 15u;
+    const unsigned mine = xcc < (unsigned)kBatchXcds ? xcc : (unsigned)kBatchXcds;
+    __hip_atomic_fetch_add(workers + mine, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(arrived, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int dom = kBatchXcds;
+    unsigned spins = 0;
+    while (ld_dev(arrived) < (unsigned)b.grid) {
+      if (++spins > kSpinLimit) { st_dev(b.status, 2u); dom = -1; break; }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (dom >= 0) {
+      bool per_xcd = mine < (unsigned)kBatchXcds && ld_dev(workers + kBatchXcds) == 0u;
+      for (int d = 0; d < kBatchXcds; ++d) per_xcd = per_xcd && ld_dev(workers + d) >= (unsigned)b.need[d];
+      dom = per_xcd ? (int)mine : kBatchXcds;
+    }
+    s_slot = dom;
+  }
+  __syncthreads();
+  const int dom = s_slot;
+  __syncthreads();
+  if (dom < 0) return;
+  const int q0 = b.qoff[dom], q1 = b.qoff[dom + 1];
+  unsigned* qctr = b.ctl + 16 * dom;
+  for (;;) {
+    if (tid == 0) {
+      const int k = (int)__hip_atomic_fetch_add(qctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_slot = k < q1 - q0 ? q0 + k : -1;
+    }
+    __syncthreads();
+    const int slot = s_slot;
+    __syncthreads();
+    if (slot < 0) break;
+    const BatchSlot t = b.slots[slot];
+    const StepArgs a = b.inst[t.inst];
+    if (b.clk && tid == 0) b.clk[2 * slot] = wall_clock64();
+    if (t.bm == 64) steps_tile<kFormFP8, DISC, false, 64>(a, t.g, t.mb, s_flag, s_local);
+    else if (t.bm == 128) steps_tile<kFormFP8, DISC, false, 128>(a, t.g, t.mb, s_flag, s_local);
+    else steps_tile<kFormFP8, DISC, false, 256>(a, t.g, t.mb, s_flag, s_local);
+    if (b.clk && tid == 0) b.clk[2 * slot + 1] = wall_clock64();
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // Reverse pass (vector-Jacobian product) of the binary32 dynamics, bSB / GbSB.
 //
@@ -663,270 +599,6 @@ __global__ void __launch_bounds__(kThreads, 1) k_adjoint(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Register-resident step kernel for the FP8 product with np <= 2048 (NKS = np/128 k-steps).
-//
-// Workgroup (g, mb) owns spins [256 mb, 256 mb + 256) of replicas [32 g, 32 g + 32); wave
-// w owns the 64 spins [256 mb + 64 w, +64) and keeps its 64 rows of J, as FP4 (exact for
-// 0 and +-1), in registers for the whole launch: 4 row tiles x NKS fragments of 16 bytes
-// per lane, k-steps [0, kAccKSteps) in accumulation registers (AGPRs, which the MFMA reads
-// directly as its A operand) and the rest in VGPRs; at np = 2048 that is 224 AGPRs of J
-// beside the 16 of the accumulators.  The four waves read the same Q fragments, which
-// come through L1.
-//
-// The 32 replica columns form two independent sub-groups of 16 (column tiles 0 and 1),
-// each with its own barrier counter, processed half a step apart:
-//   K loop (sub 0) | wait (sub 1) + first Q loads of sub 1 | update (sub 0), publish, arrive
-//   K loop (sub 1) | wait (sub 0, next step) + first loads | update (sub 1), publish, arrive
-// so every wait comes half a step after the arrivals it needs, and the first operand loads
-// of each K loop are in flight during the preceding update.
-// ---------------------------------------------------------------------------------------
-template <int NKS, bool DISC>
-__global__ void __launch_bounds__(kThreads, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) k_steps_rj(StepArgs a) {
-  __shared__ int s_flag;
-  __shared__ int s_local;
-  constexpr int kPF = kKStepsUnroll;
-  static_assert(NKS % kPF == 0 && NKS >= kPF, "k-steps must be a multiple of the prefetch depth");
-  // k-steps [0, NACC) of J in AGPRs, [NACC, NKS) in VGPRs
-  constexpr int NACC = NKS > kAccKSteps ? kAccKSteps : NKS;
-  constexpr int NVJ = NKS - NACC;
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int g = blockIdx.x % a.groups;
-  const int mb = blockIdx.x / a.groups;
-  const int row0 = mb * 256 + wave * kWaveRows;
-  const int col0 = g * kWaveCols;
-  unsigned* ctr0 = a.sync + (size_t)(2 * g) * 64;
-  unsigned* ctr1 = a.sync + (size_t)(2 * g + 1) * 64;
-  unsigned* hs = a.sync + (size_t)(2 * a.groups + g) * 64;
-  unsigned* msk = a.sync + (size_t)(3 * a.groups + g) * 64;
-  unsigned* abort_flag = a.sync + (size_t)(4 * a.groups) * 64;
-
-  // J rows of this wave (FP4 fragment-major, 1 KiB per (row tile, k-step)).
-  v4i jr[4][NACC];
-  v4i jv[4][NVJ > 0 ? NVJ : 1];
-  {
-    const uint8_t* jw = static_cast<const uint8_t*>(a.jf) + (size_t)(row0 >> 4) * NKS * 1024 + lane * 16;
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-      for (int ks = 0; ks < NKS; ++ks) {
-        v4i f = *reinterpret_cast<const v4i*>(jw + (size_t)(rt * NKS + ks) * 1024);
-        if (ks < NACC) {
-          asm volatile("" : "+a"(f));  // place it in AGPRs
-          jr[rt][ks < NACC ? ks : 0] = f;
-        } else {
-          jv[rt][ks < NACC ? 0 : ks - NACC] = f;
-        }
-      }
-  }
-
-  // State: [sub-group = column tile][row tile][v]; lane holds rows 4*(lane/16)+v of column
-  // lane%16 of each 16 x 16 tile.
-  float xs[2][4][4], ys[2][4][4], ps[2][4][4];
-#pragma unroll
-  for (int sub = 0; sub < 2; ++sub)
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
-      const int i = row0 + rt * 16 + 4 * (lane >> 4);
-      const int r = col0 + sub * 16 + (lane & 15);
-      const size_t o = (size_t)r * a.np + i;
-      const v4f vx = *reinterpret_cast<const v4f*>(a.x + o);
-      const v4f vy = *reinterpret_cast<const v4f*>(a.y + o);
-      const v4f vp = *reinterpret_cast<const v4f*>(a.p + o);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) { xs[sub][rt][v] = vx[v]; ys[sub][rt][v] = vy[v]; ps[sub][rt][v] = vp[v]; }
-    }
-
-  // Handshake: learn whether all members of this group run on one XCD.
-  if (tid == 0) {
-    const unsigned xcc = (unsigned)__builtin_amdgcn_s_getreg(kHwRegXccId) & 15u;
-    __hip_atomic_fetch_or(msk, 1u << xcc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_fetch_add(hs, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int ok = 1;
-    unsigned spins = 0;
-    while (ld_dev(hs) < (unsigned)a.nb) {
-      ++spins;
-      if ((spins & 63u) == 0 && ld_dev(abort_flag)) { ok = 0; break; }
-      if (spins > kSpinLimit) { st_dev(abort_flag, 1u); st_dev(a.status, 1u); ok = 0; break; }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    s_local = (__builtin_popcount(ld_dev(msk)) == 1) ? 1 : 0;
-    s_flag = ok;
-  }
-  __syncthreads();
-  bool alive = s_flag != 0;
-  const int local = s_local;
-
-  // arrive: this workgroup's operand stores for `ctr` are complete and counted.
-  auto arrive = [&](unsigned* ctr) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (tid == 0) {
-      if (!local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  };
-  // wait: every member has arrived `target` times on `ctr`; then this CU's L1 holds no
-  // stale copy of the operand buffer (it is invalidated), so plain loads see the data.
-  // `seen` is a count read earlier (mid K loop); when it already reaches the target the
-  // poll round trip is skipped.
-  auto wait = [&](unsigned* ctr, unsigned target, unsigned seen) -> bool {
-    if (tid == 0) {
-      int ok = 1;
-      unsigned spins = 0;
-      unsigned v = seen;
-      while (v < target) {
-        v = ld_dev(ctr);
-        ++spins;
-        if ((spins & 63u) == 0 && ld_dev(abort_flag)) { ok = 0; break; }
-        if (spins > kSpinLimit) { st_dev(abort_flag, 1u); st_dev(a.status, 1u); ok = 0; break; }
-      }
-      if (!local) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      } else {
-        asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
-      }
-      s_flag = ok;
-    }
-    __syncthreads();
-    return s_flag != 0;
-  };
-
-  const __amdgpu_buffer_rsrc_t qr = make_rsrc(a.q, 2 * a.q_buf_bytes);
-  v8i bq[kPF];
-  // Q fragment of column tile `sub`, k-step ks, in ping-pong buffer `buf`.
-  auto load_b = [&](int sub, int buf, int ks, v8i& dst) {
-    const unsigned base = (unsigned)((size_t)buf * a.q_buf_bytes) +
-                          (unsigned)(((2 * g + sub) * NKS + ks) * 2048 + lane * 16);
-    const v4i lo = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, 0));
-    const v4i hi = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base + 1024, 0, 0));
-    dst = cat(lo, hi);
-  };
-  auto prefetch = [&](int sub, int buf) {
-#pragma unroll
-    for (int u = 0; u < kPF; ++u) load_b(sub, buf, u, bq[u]);
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_sched_barrier(0);
-  };
-
-  const float A = a.A, dt = a.dt, cdt = a.cdt;
-  // Update of column tile `sub` with the product in acc (eqs. (7), (3), (4), (5), binary32,
-  // one rounding per operator), then its operand for the next step.  Written stage by
-  // stage over the 16 elements of the tile so that each stage is 16 independent operations.
-  auto update = [&](int sub, const v4f* acc, float rm, uint8_t* qnext) {
-    float t[16], u[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) { const float x = xs[sub][e >> 2][e & 3]; t[e] = x * x; }
-#pragma unroll
-    for (int e = 0; e < 16; ++e) t[e] = A * t[e];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) t[e] = 1.0f - t[e];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) t[e] = t[e] * ps[sub][e >> 2][e & 3];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) t[e] = t[e] * rm;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) ps[sub][e >> 2][e & 3] = ps[sub][e >> 2][e & 3] - t[e];  // p(t_{m+1})
-#pragma unroll
-    for (int e = 0; e < 16; ++e) t[e] = ps[sub][e >> 2][e & 3] * xs[sub][e >> 2][e & 3];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) t[e] = t[e] * dt;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) t[e] = ys[sub][e >> 2][e & 3] - t[e];            // y + dy
-#pragma unroll
-    for (int e = 0; e < 16; ++e) u[e] = cdt * acc[e >> 2][e & 3];                 // Dy
-#pragma unroll
-    for (int e = 0; e < 16; ++e) t[e] = t[e] + u[e];                              // eq. (3)
-#pragma unroll
-    for (int e = 0; e < 16; ++e) u[e] = t[e] * dt;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) u[e] = xs[sub][e >> 2][e & 3] + u[e];            // eq. (4)
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {                                                // eq. (5)
-      ys[sub][e >> 2][e & 3] = __builtin_fabsf(u[e]) > 1.0f ? 0.0f : t[e];
-      xs[sub][e >> 2][e & 3] = __builtin_amdgcn_fmed3f(u[e], -1.0f, 1.0f);
-    }
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-      store_operand<kFormFP8, DISC>(qnext, a.q_buf_bytes, NKS, row0 + rt * 16, col0 + sub * 16, lane,
-                                    xs[sub][rt]);
-  };
-
-  // Operand of the starting state for both column tiles, then the first arrivals.
-  if (alive) {
-#pragma unroll
-    for (int sub = 0; sub < 2; ++sub)
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
-        store_operand<kFormFP8, DISC>(a.q, a.q_buf_bytes, NKS, row0 + rt * 16, col0 + sub * 16, lane,
-                                      xs[sub][rt]);
-    arrive(ctr0);
-    arrive(ctr1);
-    alive = wait(ctr0, (unsigned)a.nb, 0u);
-    if (alive) prefetch(0, 0);
-  }
-
-  const int steps = a.m_end - a.m_begin;
-  for (int s = 0; alive && s < steps; ++s) {
-    const int m = a.m_begin + s;
-    const int cur = s & 1;
-    uint8_t* qnext = a.q + (size_t)(cur ^ 1) * a.q_buf_bytes;
-    const float rm = a.rtab[m];
-#pragma unroll
-    for (int sub = 0; sub < 2; ++sub) {
-      unsigned seen = 0;  // count of the other column tile's counter, read mid K loop
-      unsigned* const other = sub == 0 ? ctr1 : ctr0;
-      v4f acc[4];
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt) acc[rt] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-      for (int ks = 0; ks < NKS; ++ks) {
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-          const v4i f = ks < NACC ? jr[rt][ks < NACC ? ks : 0] : jv[rt][ks < NACC ? 0 : ks - NACC];
-          acc[rt] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(cat(f, f), bq[ks % kPF], acc[rt], 4, 0, 0,
-                                                                     127, 0, 127);
-        }
-        // Pin this k-step's MFMAs here: the empty asm reads and redefines the accumulators
-        // and, being volatile, keeps its place relative to the memory fences around the
-        // prefetches, so loads and MFMAs stay interleaved as written.
-        asm volatile("" : "+a"(acc[0]), "+a"(acc[1]), "+a"(acc[2]), "+a"(acc[3]));
-        if (ks + kPF < NKS) load_b(sub, cur, ks + kPF, bq[ks % kPF]);
-        if (ks == NKS / 2 && tid == 0) seen = ld_dev(other);
-        asm volatile("" ::: "memory");
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      // wait for the other column tile's data and start its first loads
-      if (sub == 0) {
-        alive = wait(ctr1, (unsigned)((s + 1) * a.nb), seen);
-        if (alive) prefetch(1, cur);
-      } else if (s + 1 < steps) {
-        alive = wait(ctr0, (unsigned)((s + 2) * a.nb), seen);
-        if (alive) prefetch(0, cur ^ 1);
-      }
-      if (!alive) break;
-      update(sub, acc, rm, qnext);
-      arrive(sub == 0 ? ctr0 : ctr1);
-    }
-  }
-
-#pragma unroll
-  for (int sub = 0; sub < 2; ++sub)
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
-      const int i = row0 + rt * 16 + 4 * (lane >> 4);
-      const int r = col0 + sub * 16 + (lane & 15);
-      const size_t o = (size_t)r * a.np + i;
-      *reinterpret_cast<v4f*>(a.x + o) = v4f{xs[sub][rt][0], xs[sub][rt][1], xs[sub][rt][2], xs[sub][rt][3]};
-      *reinterpret_cast<v4f*>(a.y + o) = v4f{ys[sub][rt][0], ys[sub][rt][1], ys[sub][rt][2], ys[sub][rt][3]};
-      *reinterpret_cast<v4f*>(a.p + o) = v4f{ps[sub][rt][0], ps[sub][rt][1], ps[sub][rt][2], ps[sub][rt][3]};
-    }
-}
-
-// ---------------------------------------------------------------------------------------
 // Small kernels.
 // ---------------------------------------------------------------------------------------
 __global__ void k_fill_u32(unsigned* p, size_t count, unsigned v) {
@@ -963,19 +635,6 @@ __global__ void k_encode_j(const float* j32, int np, uint8_t* jf) {
   }
 }
 
-// J (zero padded, entries in {0, +-1}) -> FP4 (E2M1) fragment-major layout of the
-// register-resident FP8 path: [row tile][k-step][lane 64][16 bytes], two values per byte,
-// low nibble first.  In the mixed FP4 x FP8 MFMA (16x16x128), FP8 byte j of lane group g
-// multiplies FP4 nibble p of the same row/column lanes with p = 16 g + j for j < 16 and
-// p = 64 + 16 g + (j - 16) for j >= 16 (p counts nibbles over the four lane groups,
-// 32 per group).  The FP8 operand layout puts k-step offset kk = 32 g + j at byte j of
-// lane group g, so nibble p must hold kk(p) below.
-__device__ __forceinline__ int fp4_pair_kk(int p) {
-  return p < 64 ? 32 * (p >> 4) + (p & 15) : 32 * ((p - 64) >> 4) + 16 + ((p - 64) & 15);
-}
-__device__ __forceinline__ unsigned fp4_code(float v) {  // exact for 0 and +-1
-  return (v < 0.0f ? 0x8u : 0u) | (__builtin_fabsf(v) == 1.0f ? 0x2u : 0u);
-}
 __global__ void k_encode_j4(const float* j32, int np, uint8_t* jf) {
   const size_t total = (size_t)np * np / 2;
   const int nks = np / kKS;
@@ -1046,6 +705,22 @@ __global__ void k_init_state(int n, int np, int rp, uint64_t seed, int mode, flo
     x[t] = xv;
     y[t] = yv;
     p[t] = 1.0f;  // p_i(0) = 1
+  }
+}
+
+// Starting state of every instance of a batch (blockIdx.y = instance), as k_init_state.
+__global__ void k_init_batch(const StepArgs* inst, const BatchInst* bi, int mode) {
+  const StepArgs& a = inst[blockIdx.y];
+  const int n = a.n, np = a.np;
+  const uint64_t seed = bi[blockIdx.y].seed;
+  const size_t total = (size_t)a.rp * np;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)(t / np), i = (int)(t % np);
+    float xv = 0.0f, yv = 0.0f;
+    if (i < n) init_elem(n, r, i, seed, mode, xv, yv);
+    a.x[t] = xv;
+    a.y[t] = yv;
+    a.p[t] = 1.0f;
   }
 }
 
@@ -1191,9 +866,10 @@ __global__ void k_energy_final(const double* partial, int nyb, int rp, int r_cou
 // J is the FP4 copy of the register-resident path; every partial sum is an integer of
 // magnitude below 2^24, so the binary32 accumulators are exact, and the per-replica
 // totals are integer atomics, hence independent of order.
-__global__ void k_sign_fp8(const float* x, int np, int nks, int rp, uint8_t* s8) {
+__device__ __forceinline__ void sign_fp8_elems(const float* x, int np, int nks, int rp, uint8_t* s8, size_t t0,
+                                               size_t stride) {
   const size_t quads = (size_t)rp * np / 4;
-  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < quads; t += (size_t)gridDim.x * blockDim.x) {
+  for (size_t t = t0; t < quads; t += stride) {
     const int r = (int)((t * 4) / np), k = (int)((t * 4) % np);
     const v4f v = *reinterpret_cast<const v4f*>(x + (size_t)r * np + k);
     unsigned w = 0x38383838u;  // +1.0 in every byte
@@ -1206,12 +882,15 @@ __global__ void k_sign_fp8(const float* x, int np, int nks, int rp, uint8_t* s8)
   }
 }
 
+__global__ void k_sign_fp8(const float* x, int np, int nks, int rp, uint8_t* s8) {
+  sign_fp8_elems(x, np, nks, rp, s8, (size_t)blockIdx.x * blockDim.x + threadIdx.x, (size_t)gridDim.x * blockDim.x);
+}
+
 // Workgroup (cg, mb): spins [256 mb, +256) (64 per wave, 4 row tiles) x replicas
 // [32 cg, +32) (2 column tiles).  G = J S over all k-steps, then sum_i s_i G_ir.
-__global__ void __launch_bounds__(256) k_energy_mfma(const uint8_t* jf4, const uint8_t* s8, const float* x, int np,
-                                                     int nks, int* eacc) {
+__device__ __forceinline__ void energy_tile(const uint8_t* jf4, const uint8_t* s8, const float* x, int np, int nks,
+                                            int* eacc, int cg, int mb) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int cg = blockIdx.x, mb = blockIdx.y;
   const int row0 = mb * 256 + wave * 64;
   v4f acc[4][2];
 #pragma unroll
@@ -1252,15 +931,19 @@ __global__ void __launch_bounds__(256) k_energy_mfma(const uint8_t* jf4, const u
   }
 }
 
+__global__ void __launch_bounds__(256) k_energy_mfma(const uint8_t* jf4, const uint8_t* s8, const float* x, int np,
+                                                     int nks, int* eacc) {
+  energy_tile(jf4, s8, x, np, nks, eacc, blockIdx.x, blockIdx.y);
+}
+
 __global__ void k_energy_final_int(const int* eacc, int r_count, double* E) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < r_count) E[r] = -0.5 * (double)eacc[r];
 }
 
-// argmin_r E_r, ties to the lowest r.
-__global__ void __launch_bounds__(256) k_best(const double* E, int r_count, int* best_idx, double* best_e) {
-  __shared__ double se[256];
-  __shared__ int si[256];
+// argmin_r E_r, ties to the lowest r (one workgroup of 256 threads).
+__device__ __forceinline__ void best_of(const double* E, int r_count, int* best_idx, double* best_e, double* se,
+                                        int* si) {
   double be = __builtin_inf();
   int bi = 0x7FFFFFFF;
   for (int r = threadIdx.x; r < r_count; r += 256) {
@@ -1282,6 +965,36 @@ __global__ void __launch_bounds__(256) k_best(const double* E, int r_count, int*
     __syncthreads();
   }
   if (threadIdx.x == 0) { *best_idx = si[0]; *best_e = se[0]; }
+}
+
+__global__ void __launch_bounds__(256) k_best(const double* E, int r_count, int* best_idx, double* best_e) {
+  __shared__ double se[256];
+  __shared__ int si[256];
+  best_of(E, r_count, best_idx, best_e, se, si);
+}
+
+// Energies and best replica of every instance of a batch (the instance is the last grid
+// dimension), from the FP4 J each instance keeps for its FP8 product.
+__global__ void k_sign_batch(const StepArgs* inst, const BatchInst* bi) {
+  const StepArgs& a = inst[blockIdx.y];
+  sign_fp8_elems(a.x, a.np, a.np / kKS, a.rp, bi[blockIdx.y].s8, (size_t)blockIdx.x * blockDim.x + threadIdx.x,
+                 (size_t)gridDim.x * blockDim.x);
+}
+
+__global__ void __launch_bounds__(256) k_energy_batch(const StepArgs* inst, const BatchInst* bi) {
+  const StepArgs& a = inst[blockIdx.z];
+  if ((int)blockIdx.y >= a.np / 256 || (int)blockIdx.x >= a.rp / 32) return;
+  const BatchInst& b = bi[blockIdx.z];
+  energy_tile(static_cast<const uint8_t*>(a.jf), b.s8, a.x, a.np, a.np / kKS, b.eacc, blockIdx.x, blockIdx.y);
+}
+
+__global__ void __launch_bounds__(256) k_energy_best_batch(const BatchInst* bi, int r_count) {
+  __shared__ double se[256];
+  __shared__ int si[256];
+  const BatchInst& b = bi[blockIdx.x];
+  for (int r = threadIdx.x; r < r_count; r += 256) b.E[r] = -0.5 * (double)b.eacc[r];
+  __syncthreads();
+  best_of(b.E, r_count, b.best_idx, b.best_e, se, si);
 }
 
 // s = sgn(x) for replicas r_first .. r_first + r_count - 1 (or the single replica
@@ -1314,15 +1027,7 @@ const void* steps_kernel() {
 
 template <bool DISC>
 const void* steps_kernel_disc(int form, int kind, int np) {
-  if (kind == kKindRegJ) {
-    switch (np / kKS) {
-      case 4: return reinterpret_cast<const void*>(&k_steps_rj<4, DISC>);
-      case 8: return reinterpret_cast<const void*>(&k_steps_rj<8, DISC>);
-      case 12: return reinterpret_cast<const void*>(&k_steps_rj<12, DISC>);
-      case 16: return reinterpret_cast<const void*>(&k_steps_rj<16, DISC>);
-      default: return nullptr;
-    }
-  }
+  if (kind == kKindRegJ) return steps_kernel_rj(np / kKS, DISC);
   switch (form) {
     case kFormFP8: return steps_kernel<kFormFP8, DISC>();
     case kFormBF16X2: return steps_kernel<kFormBF16X2, DISC>();
@@ -1492,6 +1197,43 @@ hipError_t launch_energy_fp4(const void* jf4, int np, int rp, int r_count, const
 
 hipError_t launch_best(const double* energies, int r_count, int* best_idx, double* best_e, hipStream_t stream) {
   hipLaunchKernelGGL(k_best, dim3(1), dim3(256), 0, stream, energies, r_count, best_idx, best_e);
+  return hipGetLastError();
+}
+
+hipError_t launch_steps_batch(bool discrete, const BatchArgs& b, hipStream_t stream, bool cooperative) {
+  const void* k = discrete ? reinterpret_cast<const void*>(&k_steps_batch<true>)
+                           : reinterpret_cast<const void*>(&k_steps_batch<false>);
+  BatchArgs copy = b;
+  void* args[] = {&copy};
+  if (cooperative) return hipLaunchCooperativeKernel(k, dim3(b.grid), dim3(kThreads), args, 0u, stream);
+  return hipLaunchKernel(k, dim3(b.grid), dim3(kThreads), args, 0u, stream);
+}
+
+int batch_workgroups_per_cu(bool discrete) {
+  const void* k = discrete ? reinterpret_cast<const void*>(&k_steps_batch<true>)
+                           : reinterpret_cast<const void*>(&k_steps_batch<false>);
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kThreads, 0) != hipSuccess) return 0;
+  return per_cu;
+}
+
+hipError_t launch_init_batch(const StepArgs* inst, const BatchInst* bi, int count, int np_max, int rp, int mode,
+                             hipStream_t stream) {
+  const unsigned gx = (unsigned)std::min<size_t>(grid_for((size_t)rp * np_max, 256), 1024);
+  hipLaunchKernelGGL(k_init_batch, dim3(gx, count), dim3(256), 0, stream, inst, bi, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_batch(const StepArgs* inst, const BatchInst* bi, int count, int np_max, int rp, int r_count,
+                               hipStream_t stream) {
+  if (np_max % 256 != 0 || rp % 32 != 0) return hipErrorInvalidValue;
+  const unsigned gx = (unsigned)std::min<size_t>(grid_for((size_t)rp * np_max / 4, 256), 1024);
+  hipLaunchKernelGGL(k_sign_batch, dim3(gx, count), dim3(256), 0, stream, inst, bi);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_energy_batch, dim3(rp / 32, np_max / 256, count), dim3(256), 0, stream, inst, bi);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_energy_best_batch, dim3(count), dim3(256), 0, stream, bi, r_count);
   return hipGetLastError();
 }
 

@@ -26,6 +26,9 @@ GSB_INIT_X, GSB_INIT_XY, GSB_INIT_PM01, GSB_INIT_PAIRS = 0, 1, 2, 3
 (GSB_OPT_C, GSB_OPT_PRECISION, GSB_OPT_INIT_MODE, GSB_OPT_LAMBDA_MAX, GSB_OPT_LAMBDA_MIN, GSB_OPT_N,
  GSB_OPT_STEP, GSB_OPT_REPLICAS, GSB_OPT_DT_STABLE, GSB_OPT_N_DYN) = range(10)
 
+(GSB_BATCH_C, GSB_BATCH_DT, GSB_BATCH_LAMBDA_MAX, GSB_BATCH_LAMBDA_MIN, GSB_BATCH_TILE_ROWS, GSB_BATCH_STEP_US,
+ GSB_BATCH_N, GSB_BATCH_GRAPH, GSB_BATCH_INIT_MODE, GSB_BATCH_COUNT, GSB_BATCH_REPLICAS, GSB_BATCH_GRID) = range(12)
+
 VARIANTS = {"bsb": GSB_BSB, "dsb": GSB_DSB, "gbsb": GSB_GBSB, "gsb": GSB_GBSB, "gdsb": GSB_GDSB}
 PRECISIONS = {"fp32": GSB_PREC_FP32, "bf16x2": GSB_PREC_BF16X2, "fp8": GSB_PREC_FP8, "fix16": GSB_PREC_FIX16}
 
@@ -36,7 +39,10 @@ STATUS_NAMES = {0: "GSB_OK", -1: "GSB_EINVAL", -2: "GSB_ENOTSYM", -3: "GSB_EDIAG
 SYMBOLS = ("gsb_create", "gsb_destroy", "gsb_set", "gsb_get", "gsb_set_stream", "gsb_workspace_size",
            "gsb_bind_workspace", "gsb_init", "gsb_step", "gsb_run", "gsb_energy", "gsb_best", "gsb_spins",
            "gsb_state", "gsb_set_state", "gsb_delta", "gsb_lle_workspace_size", "gsb_lle", "gsb_vjp", "gsb_last_step_ms",
-           "gsb_last_error", "gsb_version")
+           "gsb_batch_create", "gsb_batch_destroy", "gsb_batch_set_stream", "gsb_batch_workspace_size",
+           "gsb_batch_bind_workspace", "gsb_batch_set_coupling", "gsb_batch_set", "gsb_batch_get", "gsb_batch_autotune",
+           "gsb_batch_run", "gsb_batch_energy", "gsb_batch_best", "gsb_batch_state", "gsb_batch_last_ms",
+           "gsb_batch_plan", "gsb_last_error", "gsb_version")
 
 
 class GsbError(RuntimeError):
@@ -85,6 +91,21 @@ def load_library(path: str = LIB_PATH):
         "gsb_lle": (i32, [vp, i32, i32, dbl, vp, dbl, i32, i32, u64, u64, i32, vp, vp]),
         "gsb_vjp": (i32, [vp, i32, vp, vp, vp]),
         "gsb_last_step_ms": (i32, [vp, ctypes.POINTER(dbl)]),
+        "gsb_batch_create": (i32, [i32, vp, i32, ctypes.POINTER(vp)]),
+        "gsb_batch_destroy": (None, [vp]),
+        "gsb_batch_set_stream": (i32, [vp, vp]),
+        "gsb_batch_workspace_size": (i32, [vp, ctypes.POINTER(sz)]),
+        "gsb_batch_bind_workspace": (i32, [vp, vp, sz]),
+        "gsb_batch_set_coupling": (i32, [vp, i32, vp, dbl, dbl]),
+        "gsb_batch_set": (i32, [vp, i32, i32, dbl]),
+        "gsb_batch_get": (i32, [vp, i32, i32, ctypes.POINTER(dbl)]),
+        "gsb_batch_autotune": (i32, [vp, i32, dbl, i32, u64]),
+        "gsb_batch_run": (i32, [vp, i32, dbl, i32, u64]),
+        "gsb_batch_energy": (i32, [vp, i32, vp]),
+        "gsb_batch_best": (i32, [vp, vp, vp]),
+        "gsb_batch_state": (i32, [vp, i32, vp, vp, vp]),
+        "gsb_batch_last_ms": (i32, [vp, ctypes.POINTER(dbl)]),
+        "gsb_batch_plan": (i32, [i32, vp, vp, vp, i32, i32, vp, vp]),
         "gsb_last_error": (ctypes.c_char_p, []),
         "gsb_version": (ctypes.c_char_p, []),
     }
@@ -251,6 +272,183 @@ def gsb_last_step_ms(ctx) -> float:
     v = ctypes.c_double()
     _check(load_library().gsb_last_step_ms(ctx, ctypes.byref(v)), "gsb_last_step_ms")
     return v.value
+
+
+def gsb_batch_create(n, replicas: int):
+    nn = np.ascontiguousarray(n, dtype=np.int32)
+    out = ctypes.c_void_p()
+    _check(load_library().gsb_batch_create(int(nn.size), _ptr(nn), replicas, ctypes.byref(out)), "gsb_batch_create")
+    return out
+
+
+def gsb_batch_destroy(batch) -> None:
+    load_library().gsb_batch_destroy(batch)
+
+
+def gsb_batch_set_stream(batch, stream: int | None) -> None:
+    _check(load_library().gsb_batch_set_stream(batch, ctypes.c_void_p(stream or 0)), "gsb_batch_set_stream")
+
+
+def gsb_batch_workspace_size(batch) -> int:
+    v = ctypes.c_size_t()
+    _check(load_library().gsb_batch_workspace_size(batch, ctypes.byref(v)), "gsb_batch_workspace_size")
+    return v.value
+
+
+def gsb_batch_bind_workspace(batch, device_ptr: int, nbytes: int) -> None:
+    _check(load_library().gsb_batch_bind_workspace(batch, ctypes.c_void_p(device_ptr), nbytes),
+           "gsb_batch_bind_workspace")
+
+
+def gsb_batch_set_coupling(batch, k: int, J: np.ndarray, c: float = 0.0, dt: float = 0.0) -> None:
+    J = np.ascontiguousarray(J, dtype=np.float32)
+    if J.ndim != 2 or J.shape[0] != J.shape[1]:
+        raise ValueError("J must be a square matrix")
+    _check(load_library().gsb_batch_set_coupling(batch, k, _ptr(J), float(c), float(dt)), "gsb_batch_set_coupling")
+
+
+def gsb_batch_set(batch, k: int, option: int, value: float) -> None:
+    _check(load_library().gsb_batch_set(batch, k, option, float(value)), "gsb_batch_set")
+
+
+def gsb_batch_get(batch, k: int, option: int) -> float:
+    v = ctypes.c_double()
+    _check(load_library().gsb_batch_get(batch, k, option, ctypes.byref(v)), "gsb_batch_get")
+    return v.value
+
+
+def gsb_batch_autotune(batch, variant: int, control_strength: float, trial_steps: int, seed: int) -> None:
+    _check(load_library().gsb_batch_autotune(batch, variant, control_strength, trial_steps, seed & (2**64 - 1)),
+           "gsb_batch_autotune")
+
+
+def gsb_batch_run(batch, variant: int, control_strength: float, steps: int, seed: int) -> None:
+    _check(load_library().gsb_batch_run(batch, variant, control_strength, steps, seed & (2**64 - 1)), "gsb_batch_run")
+
+
+def gsb_batch_energy(batch, k: int) -> np.ndarray:
+    E = np.empty(int(gsb_batch_get(batch, -1, GSB_BATCH_REPLICAS)), dtype=np.float64)
+    _check(load_library().gsb_batch_energy(batch, k, _ptr(E)), "gsb_batch_energy")
+    return E
+
+
+def gsb_batch_best(batch):
+    count = int(gsb_batch_get(batch, -1, GSB_BATCH_COUNT))
+    e = np.empty(count, dtype=np.float64)
+    r = np.empty(count, dtype=np.int32)
+    _check(load_library().gsb_batch_best(batch, _ptr(e), _ptr(r)), "gsb_batch_best")
+    return e, r
+
+
+def gsb_batch_state(batch, k: int):
+    R = int(gsb_batch_get(batch, -1, GSB_BATCH_REPLICAS))
+    n = int(gsb_batch_get(batch, k, GSB_BATCH_N))
+    x, y, p = (np.empty((R, n), dtype=np.float32) for _ in range(3))
+    _check(load_library().gsb_batch_state(batch, k, _ptr(x), _ptr(y), _ptr(p)), "gsb_batch_state")
+    return x, y, p
+
+
+def gsb_batch_last_ms(batch) -> float:
+    v = ctypes.c_double()
+    _check(load_library().gsb_batch_last_ms(batch, ctypes.byref(v)), "gsb_batch_last_ms")
+    return v.value
+
+
+def gsb_batch_plan(width, gangs, cost, queues: int, workers: int):
+    """Queue and rank of every unit in the plan gsb_batch_run uses."""
+    w = np.ascontiguousarray(width, dtype=np.int32)
+    g = np.ascontiguousarray(gangs, dtype=np.int32)
+    c = np.ascontiguousarray(cost, dtype=np.float64)
+    q = np.empty(w.size, dtype=np.int32)
+    r = np.empty(w.size, dtype=np.int32)
+    _check(load_library().gsb_batch_plan(int(w.size), _ptr(w), _ptr(g), _ptr(c), queues, workers, _ptr(q), _ptr(r)),
+           "gsb_batch_plan")
+    return q, r
+
+
+class Batch:
+    """Many instances of different sizes, all replicas in one persistent launch (FP8 product).
+
+    >>> b = Batch([n0, n1, ...], replicas=128)
+    >>> b.set_couplings(lambda k: J_k)           # c = 1/lambda_max, dt from eq. (13)
+    >>> b.autotune("gbsb", A=0.2, trial_steps=50, seed=1)
+    >>> b.run("gbsb", A=0.2, steps=1000, seed=1)
+    >>> energies, replicas = b.best()
+    """
+
+    def __init__(self, sizes, replicas: int):
+        import torch  # device memory and streams only
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("Batch needs a HIP device")
+        self._torch = torch
+        self.sizes = [int(v) for v in sizes]
+        self.replicas = int(replicas)
+        self.b = gsb_batch_create(self.sizes, self.replicas)
+        need = gsb_batch_workspace_size(self.b)
+        self._ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+        base = self._ws.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        gsb_batch_bind_workspace(self.b, aligned, need + 256 - (aligned - base))
+        gsb_batch_set_stream(self.b, torch.cuda.current_stream().cuda_stream)
+
+    def close(self):
+        if self.b is not None:
+            gsb_batch_destroy(self.b)
+            self.b = None
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_coupling(self, k: int, J, c: float = 0.0, dt: float = 0.0):
+        gsb_batch_set_coupling(self.b, k, J, c, dt)
+
+    def set_couplings(self, make, threads: int = 8):
+        """make(k) -> J or (J, c, dt); the instances are generated and uploaded by a pool of
+        host threads (the library call releases the interpreter lock)."""
+        from concurrent.futures import ThreadPoolExecutor
+
+        def one(k):
+            v = make(k)
+            J, c, dt = (v if isinstance(v, tuple) else (v, 0.0, 0.0))
+            gsb_batch_set_coupling(self.b, k, J, c, dt)
+
+        with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+            list(ex.map(one, range(len(self.sizes))))
+
+    def set(self, k: int, option: int, value: float):
+        gsb_batch_set(self.b, k, option, value)
+
+    def get(self, k: int, option: int) -> float:
+        return gsb_batch_get(self.b, k, option)
+
+    def autotune(self, variant, *, A: float = 0.0, trial_steps: int = 50, seed: int = 1):
+        v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        gsb_batch_autotune(self.b, v, A, trial_steps, seed)
+
+    def run(self, variant, *, A: float = 0.0, steps: int, seed: int):
+        v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        gsb_batch_set_stream(self.b, self._torch.cuda.current_stream().cuda_stream)
+        gsb_batch_run(self.b, v, A, steps, seed)
+
+    def energy(self, k: int) -> np.ndarray:
+        return gsb_batch_energy(self.b, k)
+
+    def best(self):
+        return gsb_batch_best(self.b)
+
+    def state(self, k: int):
+        return gsb_batch_state(self.b, k)
+
+    def last_ms(self) -> float:
+        return gsb_batch_last_ms(self.b)
+
+    def params(self, k: int):
+        return gsb_batch_get(self.b, k, GSB_BATCH_C), gsb_batch_get(self.b, k, GSB_BATCH_DT)
 
 
 class GSB:

@@ -31,8 +31,10 @@ def splitmix64(seed: int, k: np.ndarray) -> np.ndarray:
 
 def _upper(n: int, draws: np.ndarray) -> np.ndarray:
     J = np.zeros((n, n), dtype=np.float32)
-    iu = np.triu_indices(n, 1)
-    J[iu] = draws
+    o = 0
+    for i in range(n - 1):  # row-major upper triangle, row by row
+        J[i, i + 1:] = draws[o:o + n - 1 - i]
+        o += n - 1 - i
     return J + J.T
 
 
@@ -69,3 +71,26 @@ def erdos_renyi_pm1(n: int, prob: float, seed: int) -> np.ndarray:
 def paper_c(n: int) -> float:
     """c = 1/(2 sqrt(N) sigma) with sigma = 1 for J_ij in {+-1} (App. A)."""
     return 1.0 / (2.0 * np.sqrt(n))
+
+
+def batch_workload(count: int, seed: int, n_min: int = 64, n_max: int = 4096):
+    """Specs of a batch of uneven instances: n iid uniform integer in [n_min, n_max]; even
+    indices dense +-1, odd indices Erdos-Renyi with edge probability p iid U[0.01, 0.06]
+    and +-1 weights.  Spec k uses draws 3k+1 (n), 3k+2 (p) and 3k+3 (the instance's own
+    generator seed) of stream `seed`.  Returns a list of (kind, n, p, instance_seed)."""
+    z = splitmix64(seed, np.arange(1, 3 * count + 1, dtype=np.uint64))
+    specs = []
+    for k in range(count):
+        n = n_min + int(z[3 * k] % np.uint64(n_max - n_min + 1))
+        u = float(z[3 * k + 1] >> np.uint64(11)) * 2.0**-53
+        iseed = int(z[3 * k + 2] >> np.uint64(1))
+        if k % 2 == 0:
+            specs.append(("dense", n, 1.0, iseed))
+        else:
+            specs.append(("sparse", n, 0.01 + 0.05 * u, iseed))
+    return specs
+
+
+def make_instance(spec) -> np.ndarray:
+    kind, n, p, iseed = spec
+    return dense_pm1(n, iseed) if kind == "dense" else erdos_renyi_pm1(n, p, iseed)

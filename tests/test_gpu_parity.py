@@ -162,6 +162,28 @@ def test_full_size_sampled_bitexact(orc, variant):
     check_exact(E, orc.energy(J, spins), "energies")
 
 
+@pytest.mark.parametrize("variant", ["gbsb", "gdsb"])
+def test_fp8_generic_kernel_bitexact(orc, variant):
+    # N_p > 2048: the FP8 product runs in the generic kernel (FP4 J from L2), 2 k-step
+    # rounds of the software pipeline and a ragged tail of 472 padded spins.
+    n, R, M, A, seed = 2600, 128, 40, 0.25, 31
+    say(f"case fp8 generic variant={variant} n={n} R={R} M={M}")
+    J = instances.dense_pm1(n, 12)
+    c = instances.paper_c(n)
+    g = make(J, "fp8", c)
+    g.run(variant, A=A, dt=1.25, replicas=R, steps=M, seed=seed)
+    x, y, p, _ = g.state()
+    E = g.energy()
+    g.close()
+    sample = np.array([0, 63, 127])
+    x0, y0, p0 = oracle_start(orc, n, R, seed, orc.INIT_X)
+    form = orc.FORM_E4M3 if variant == "gbsb" else orc.FORM_EXACT
+    xo, yo, po = orc.run(J, orc.VARIANTS[variant], A=A, dt=1.25, c=c, steps=M, x=x0[sample], y=y0[sample],
+                         p=p0[sample], form=form, mode="fp32")
+    check_exact(x[sample], xo, "x"); check_exact(y[sample], yo, "y"); check_exact(p[sample], po, "p")
+    check_exact(E, orc.energy(J, orc.spins(x)), "energies")
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16x2"])
 def test_continuous_forms_error_bounds(orc, precision):
     # bSB with a continuous product: one step from an identical state, and 100 steps.
