@@ -111,7 +111,7 @@ struct gsb_batch {
   float* d_rtab = nullptr;
   unsigned long long* d_clk = nullptr;
   // device facts
-  int per_cu = 0, grid = 0, cap = 0;
+  int per_cu = 0, grid = 0, cap = 0, lds_bytes = 0;
   double wall_hz = 0;
   // run
   bool ran = false;
@@ -130,11 +130,15 @@ namespace {
 
 gsb_status device_facts(gsb_batch* b) {
   if (b->grid) return GSB_OK;
-  int dev = 0, cus = 0, rate_khz = 0;
+  int dev = 0, cus = 0, rate_khz = 0, lds_max = 0;
   BHIP(hipGetDevice(&dev), "hipGetDevice");
   BHIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "device attribute");
   BHIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev), "device attribute");
-  const int a = batch_workgroups_per_cu(false), d = batch_workgroups_per_cu(true);
+  BHIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "device attribute");
+  // the step kernel runs one workgroup per CU (registers), so J rows may fill the LDS
+  // beside the kernel's own few bytes
+  b->lds_bytes = std::max(0, std::min(lds_max, 160 * 1024) - 1024) / 1024 * 1024;
+  const int a = batch_workgroups_per_cu(false, b->lds_bytes), d = batch_workgroups_per_cu(true, b->lds_bytes);
   b->per_cu = std::min(a, d);
   if (b->per_cu < 1) return bfail(GSB_EDEVICE, "occupancy query failed for the batched step kernel");
   b->grid = b->per_cu * cus;
@@ -376,6 +380,7 @@ gsb_status enqueue_run(gsb_batch* b, bool discrete, bool cooperative, bool timed
   a.status = reinterpret_cast<unsigned*>(w + b->off_status);
   a.clk = b->d_clk;
   a.grid = b->grid;
+  a.lds_bytes = b->lds_bytes;
   if (timed) BHIP(hipEventRecord(b->ev0, st), "event record");
   BHIP(launch_steps_batch(discrete, a, st, cooperative), "batched step kernel launch");
   if (timed) BHIP(hipEventRecord(b->ev1, st), "event record");

@@ -17,7 +17,10 @@ typedef unsigned v2u __attribute__((ext_vector_type(2)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
-constexpr int kPolicySc1 = 16;             // buffer-load cache policy: device scope (skips L1)
+// Cache policy of operand loads: plain (L1 and L2 cacheable).  Every barrier that
+// publishes an operand buffer invalidates the reader CU's L1 (group_sync), so no stale
+// line survives; device-scope loads instead go past L2 and cost ~1.5 us each.
+constexpr int kPolicyPlain = 0;
 constexpr unsigned kSpinLimit = 1u << 22;  // polls before a barrier gives up (seconds)
 constexpr int kHwRegXccId = 20 | (0 << 6) | ((4 - 1) << 11);  // hwreg(HW_REG_XCC_ID, 0, 4)
 
@@ -39,9 +42,9 @@ __device__ __forceinline__ void st_dev(unsigned* p, unsigned v) {
 // Barrier over the `nb` workgroups that share a replica group.  Every wave first waits
 // until its own stores are acknowledged (they are then in L2), then one thread counts
 // the workgroup in and polls the counter with device-scope loads.  When all members sit
-// on one XCD (`local`) they share that XCD's L2, and operand loads that skip L1 see the
-// data without any cache maintenance; otherwise the agent-scope release/acquire fences
-// write back and invalidate the caches between XCDs.
+// on one XCD (`local`) they share that XCD's L2: invalidating this CU's L1 is all the
+// cache maintenance the next operand loads need; otherwise the agent-scope
+// release/acquire fences write back and invalidate the caches between XCDs.
 __device__ __forceinline__ bool group_sync(unsigned* ctr, unsigned target, int local,
                                            unsigned* abort_flag, unsigned* status, int* s_flag) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -57,7 +60,11 @@ __device__ __forceinline__ bool group_sync(unsigned* ctr, unsigned target, int l
       if ((spins & 63u) == 0 && ld_dev(abort_flag)) { ok = 0; break; }
       if (spins > kSpinLimit) { st_dev(abort_flag, 1u); st_dev(status, 1u); ok = 0; break; }
     }
-    if (!local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (!local) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    } else {
+      asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+    }
     *s_flag = ok;
   }
   __syncthreads();

@@ -91,6 +91,7 @@ struct BatchArgs {
   unsigned* status;           // 1: a gang barrier timed out; 2: the start-up count did
   unsigned long long* clk;    // per slot: wall-clock ticks at start and end, or nullptr
   int grid;                   // workgroups of the launch (all co-resident)
+  int lds_bytes;              // dynamic LDS per workgroup for J rows (0: J from L2 / MALL)
 };
 
 // ---- launchers (all asynchronous on `stream`) ----
@@ -140,7 +141,7 @@ hipError_t launch_spins(const float* x, int n_out, int np, int r_first, int r_co
 // its co-resident workgroups per CU, and the per-instance start, energy and best kernels
 // over `count` instances (np_max: the largest np; rp replicas each, r_count of them real).
 hipError_t launch_steps_batch(bool discrete, const BatchArgs& b, hipStream_t stream, bool cooperative);
-int batch_workgroups_per_cu(bool discrete);
+int batch_workgroups_per_cu(bool discrete, int lds_bytes);
 hipError_t launch_init_batch(const StepArgs* inst, const BatchInst* bi, int count, int np_max, int rp, int mode,
                              hipStream_t stream);
 hipError_t launch_energy_batch(const StepArgs* inst, const BatchInst* bi, int count, int np_max, int rp,

@@ -36,7 +36,7 @@ __device__ __forceinline__ void gemm_tile_fp32(const uint8_t* jrows, __amdgpu_bu
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct) {
         const unsigned base = (unsigned)(((size_t)((rb0 + ct) * nks + ks) * 8 + grp) * 1024 + lane * 16);
-        bq[ct] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kPolicySc1));
+        bq[ct] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kPolicyPlain));
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t)
@@ -58,6 +58,10 @@ __device__ __forceinline__ void gemm_tile_fp32(const uint8_t* jrows, __amdgpu_bu
 // synchronise every step.  For the FP8 product J is read as FP4 (E2M1, exact for 0 and
 // +-1; the FP8 form requires J in {0, +-1}), half the bytes of FP8.
 //
+// With `lds_j` (FP8 product) the workgroup first copies the leading k-steps of its J rows
+// into LDS, as many as `lds_bytes` holds (all of them for 64 rows up to np = 4096 in
+// 128 KiB), and reads those from LDS every step: J then costs no L2, MALL or HBM traffic.
+//
 // k_steps runs one tile per workgroup, b = (g, mb) = (b mod groups, b div groups): with
 // 8 or 16 groups, round-robin dispatch puts each group on one XCD.
 //
@@ -68,15 +72,18 @@ __device__ __forceinline__ void gemm_tile_fp32(const uint8_t* jrows, __amdgpu_bu
 // eqs. (7), (3), (4), (5) (see the update below); the control strength may differ per
 // replica (a.acol).
 // ---------------------------------------------------------------------------------------
-template <int FORM, bool DISC, bool TANG, int BM>
-__device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int& s_flag, int& s_local) {
+template <int FORM, bool DISC, bool TANG, int BM, bool LJ = false>
+__device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int& s_flag, int& s_local,
+                                           uint8_t* lds_j = nullptr, int lds_bytes = 0) {
+  static_assert(!LJ || FORM == kFormFP8, "J rows in LDS: FP8 product (FP4 J) only");
   static_assert(!TANG || (FORM == kFormFP32 && !DISC), "the tangent needs the continuous binary32 product");
   static_assert(BM == 64 || BM == 128 || BM == 256, "tile rows");
   constexpr int BN = 8192 / BM;
   constexpr int WCOLS = BN / kWaveCols;  // waves across the replica columns
-  constexpr int kQPolicy = kPolicySc1;   // each wave reads its own columns: skip L1
+  constexpr int kQPolicy = kPolicyPlain;  // L1 is invalidated at every barrier
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the wave index is uniform within a wave; readfirstlane tells the compiler so
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wrow = wave / WCOLS;             // 64-row slice of the workgroup's rows
   const int row0 = mb * BM + wrow * kWaveRows;
   const int col0 = g * BN + (wave % WCOLS) * kWaveCols;
@@ -106,6 +113,26 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
 #pragma unroll
       for (int v = 0; v < 4; ++v) { xs[rt][ct][v] = vx[v]; ys[rt][ct][v] = vy[v]; ps[rt][ct][v] = vp[v]; }
     }
+
+  // Leading k-steps of this workgroup's J rows into LDS: [row tile][k-step][lane][16 B].
+  int nks_l = 0;
+  if constexpr (LJ) {
+    {
+      constexpr int kTilesWG = BM / 16;
+      nks_l = min(nks, lds_bytes / (kTilesWG * 1024)) / kKStepsUnroll * kKStepsUnroll;
+      const uint8_t* jwg = static_cast<const uint8_t*>(a.jf) + (size_t)(mb * kTilesWG) * nks * 1024;
+      const int chunks = kTilesWG * nks_l * 64;
+      for (int c = tid; c < chunks; c += kThreads) {
+        const int t = c / (nks_l * 64), rem = c - t * (nks_l * 64);
+        const int ks = rem >> 6, l = rem & 63;
+        *reinterpret_cast<v4i*>(lds_j + (size_t)c * 16) =
+            *reinterpret_cast<const v4i*>(jwg + ((size_t)t * nks + ks) * 1024 + l * 16);
+      }
+      __syncthreads();
+    }
+  }
+  // this wave's row tiles in LDS
+  const uint8_t* jlds = LJ ? lds_j + (size_t)(4 * wrow) * nks_l * 1024 + lane * 16 : nullptr;
 
   // Handshake: learn whether all members of this group run on one XCD.
   if (tid == 0) {
@@ -155,9 +182,12 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
 
     if constexpr (FORM == kFormFP8) {
       // Software pipeline: Q fragments are fetched kPF k-steps ahead and FP4 J fragments
-      // one k-step ahead, so neither latency stalls the MFMA stream.  nks is a multiple
-      // of kPF (np is padded to 512); the main loop prefetches unconditionally and the
-      // last kPF k-steps are peeled without loads.
+      // one k-step ahead, so neither latency stalls the MFMA stream.  The k-steps run in
+      // two segments, [0, nks_l) with J from LDS and [nks_l, nks) with J from L2, each a
+      // pipeline of its own: J registers are then never written by an LDS read while a
+      // global load to them may be in flight (which would force a full wait).  Segment
+      // lengths are multiples of kPF; each prefetches unconditionally and peels its last
+      // kPF k-steps without loads.
       constexpr int kPF = kKStepsUnroll;
       v8i bq[kPF][2];
       v4i aj[2][4];
@@ -170,10 +200,14 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
           dst[ct] = cat(lo, hi);
         }
       };
-      auto load_a = [&](int ks, v4i* dst) {
+      auto load_a_glb = [&](int ks, v4i* dst) {
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt)
           dst[rt] = *reinterpret_cast<const v4i*>(jrows + (size_t)(rt * nks + ks) * 1024 + lane * 16);
+      };
+      auto load_a_lds = [&](int ks, v4i* dst) {
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) dst[rt] = *reinterpret_cast<const v4i*>(jlds + (size_t)(rt * nks_l + ks) * 1024);
       };
       auto mfmas = [&](const v4i* aa, const v8i* bb) {
         // A: FP4 (format code 4, the upper four registers unused), B: FP8 E4M3, unit scales
@@ -184,27 +218,33 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
             acc[rt][ct] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(cat(aa[rt], aa[rt]), bb[ct], acc[rt][ct],
                                                                            4, 0, 0, 127, 0, 127);
       };
+      auto segment = [&](int k0, int k1, auto load_a) {
 #pragma unroll
-      for (int u = 0; u < kPF; ++u) load_b(u, bq[u]);
-      load_a(0, aj[0]);
-      int ks0 = 0;
-      for (; ks0 < nks - kPF; ks0 += kPF) {
+        for (int u = 0; u < kPF; ++u) load_b(k0 + u, bq[u]);
+        load_a(k0, aj[0]);
+        int ks0 = k0;
+        for (; ks0 < k1 - kPF; ks0 += kPF) {
+#pragma unroll
+          for (int u = 0; u < kPF; ++u) {
+            load_a(ks0 + u + 1, aj[(u + 1) & 1]);
+            __builtin_amdgcn_sched_barrier(0);  // keep each prefetch ahead of the MFMAs
+            mfmas(aj[u & 1], bq[u]);
+            load_b(ks0 + u + kPF, bq[u]);
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
 #pragma unroll
         for (int u = 0; u < kPF; ++u) {
-          load_a(ks0 + u + 1, aj[(u + 1) & 1]);
-          __builtin_amdgcn_sched_barrier(0);  // keep each prefetch ahead of the MFMAs
+          if (u + 1 < kPF) load_a(ks0 + u + 1, aj[(u + 1) & 1]);
+          __builtin_amdgcn_sched_barrier(0);
           mfmas(aj[u & 1], bq[u]);
-          load_b(ks0 + u + kPF, bq[u]);
           __builtin_amdgcn_sched_barrier(0);
         }
+      };
+      if constexpr (LJ) {
+        if (nks_l > 0) segment(0, nks_l, load_a_lds);
       }
-#pragma unroll
-      for (int u = 0; u < kPF; ++u) {
-        if (u + 1 < kPF) load_a(ks0 + u + 1, aj[(u + 1) & 1]);
-        __builtin_amdgcn_sched_barrier(0);
-        mfmas(aj[u & 1], bq[u]);
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      if (nks_l < nks) segment(nks_l, nks, load_a_glb);
     } else if constexpr (FORM == kFormBF16X2) {
       constexpr int planes = DISC ? 1 : 2;  // sgn(x) has no low part
       for (int ks = 0; ks < nks; ++ks) {
@@ -221,7 +261,7 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct) {
               const unsigned base = (unsigned)(pl * plane_bytes + ((size_t)((rb0 + ct) * nks + ks) * 4 + sub) * 1024 + lane * 16);
-              bq[ct] = __builtin_bit_cast(v8bf, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kPolicySc1));
+              bq[ct] = __builtin_bit_cast(v8bf, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kPolicyPlain));
             }
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt)
@@ -256,7 +296,7 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
             for (int ct = 0; ct < 2; ++ct) {
               const unsigned base =
                   (unsigned)(pl * plane_bytes + ((size_t)((rb0 + ct) * nks + ks) * 2 + half) * 1024 + lane * 16);
-              bq[ct] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kPolicySc1));
+              bq[ct] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kPolicyPlain));
             }
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt)
@@ -403,11 +443,40 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
 // on each XCD at start-up and, if any queue lacks workers, every workgroup serves the
 // device-wide queue instead (whose gangs all fit in the grid).
 // ---------------------------------------------------------------------------------------
+// Table entries are read with vector loads (the tables are not provably read-only), so
+// the compiler takes every field as per-lane; the fields are the same in all lanes, and
+// reading them through readfirstlane keeps arguments, descriptors and branches scalar.
+__device__ __forceinline__ int ufirst(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float ufirst(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ uint64_t ufirst64(uint64_t v) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+template <class T>
+__device__ __forceinline__ T* ufirst(T* p) { return reinterpret_cast<T*>(ufirst64(reinterpret_cast<uint64_t>(p))); }
+
+__device__ __forceinline__ StepArgs uniform_args(const StepArgs& a) {
+  StepArgs u;
+  u.n = ufirst(a.n); u.np = ufirst(a.np); u.rp = ufirst(a.rp); u.groups = ufirst(a.groups); u.nb = ufirst(a.nb);
+  u.discrete = ufirst(a.discrete); u.m_begin = ufirst(a.m_begin); u.m_end = ufirst(a.m_end);
+  u.A = ufirst(a.A); u.dt = ufirst(a.dt); u.cdt = ufirst(a.cdt);
+  u.acol = ufirst(a.acol); u.rtab = ufirst(a.rtab); u.jf = ufirst(a.jf); u.q = ufirst(a.q);
+  u.q_buf_bytes = (size_t)ufirst64(a.q_buf_bytes);
+  u.x = ufirst(a.x); u.y = ufirst(a.y); u.p = ufirst(a.p);
+  u.sync = ufirst(a.sync); u.status = ufirst(a.status);
+  u.tape = ufirst(a.tape); u.tape_arr = (size_t)ufirst64(a.tape_arr);
+  return u;
+}
+
 template <bool DISC>
 __global__ void __launch_bounds__(kThreads, 1) k_steps_batch(BatchArgs b) {
   __shared__ int s_flag;
   __shared__ int s_local;
   __shared__ int s_slot;
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds_dyn[];  // b.lds_bytes: J rows of the current tile
   const int tid = threadIdx.x;
   unsigned* workers = b.ctl + 160;  // [kBatchXcds + 1]: per XCD, then any other XCC id
   unsigned* arrived = b.ctl + 192;
@@ -431,7 +500,9 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps_batch(BatchArgs b) {
     s_slot = dom;
   }
   __syncthreads();
-  const int dom = s_slot;
+  // values read from LDS are per-lane to the compiler: make them uniform (scalar), so the
+  // tile's arguments, buffer descriptors and branches stay scalar
+  const int dom = __builtin_amdgcn_readfirstlane(s_slot);
   __syncthreads();
   if (dom < 0) return;
   const int q0 = b.qoff[dom], q1 = b.qoff[dom + 1];
@@ -442,15 +513,17 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps_batch(BatchArgs b) {
       s_slot = k < q1 - q0 ? q0 + k : -1;
     }
     __syncthreads();
-    const int slot = s_slot;
+    const int slot = __builtin_amdgcn_readfirstlane(s_slot);
     __syncthreads();
     if (slot < 0) break;
-    const BatchSlot t = b.slots[slot];
-    const StepArgs a = b.inst[t.inst];
+    const BatchSlot tv = b.slots[slot];
+    const BatchSlot t{ufirst(tv.inst), ufirst(tv.g), ufirst(tv.mb), ufirst(tv.bm)};
+    const StepArgs a = uniform_args(b.inst[t.inst]);
     if (b.clk && tid == 0) b.clk[2 * slot] = wall_clock64();
-    if (t.bm == 64) steps_tile<kFormFP8, DISC, false, 64>(a, t.g, t.mb, s_flag, s_local);
-    else if (t.bm == 128) steps_tile<kFormFP8, DISC, false, 128>(a, t.g, t.mb, s_flag, s_local);
-    else steps_tile<kFormFP8, DISC, false, 256>(a, t.g, t.mb, s_flag, s_local);
+    if (t.bm == 64) steps_tile<kFormFP8, DISC, false, 64, true>(a, t.g, t.mb, s_flag, s_local, lds_dyn, b.lds_bytes);
+    else if (t.bm == 128) steps_tile<kFormFP8, DISC, false, 128, true>(a, t.g, t.mb, s_flag, s_local, lds_dyn, b.lds_bytes);
+    else steps_tile<kFormFP8, DISC, false, 256, true>(a, t.g, t.mb, s_flag, s_local, lds_dyn, b.lds_bytes);
+    __syncthreads();  // the next tile overwrites the LDS copy of J
     if (b.clk && tid == 0) b.clk[2 * slot + 1] = wall_clock64();
   }
 }
@@ -1203,17 +1276,23 @@ hipError_t launch_best(const double* energies, int r_count, int* best_idx, doubl
 hipError_t launch_steps_batch(bool discrete, const BatchArgs& b, hipStream_t stream, bool cooperative) {
   const void* k = discrete ? reinterpret_cast<const void*>(&k_steps_batch<true>)
                            : reinterpret_cast<const void*>(&k_steps_batch<false>);
+  if (b.lds_bytes > 0) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, b.lds_bytes);
+    if (e != hipSuccess) return e;
+  }
   BatchArgs copy = b;
   void* args[] = {&copy};
-  if (cooperative) return hipLaunchCooperativeKernel(k, dim3(b.grid), dim3(kThreads), args, 0u, stream);
-  return hipLaunchKernel(k, dim3(b.grid), dim3(kThreads), args, 0u, stream);
+  if (cooperative) return hipLaunchCooperativeKernel(k, dim3(b.grid), dim3(kThreads), args, (unsigned)b.lds_bytes, stream);
+  return hipLaunchKernel(k, dim3(b.grid), dim3(kThreads), args, (size_t)b.lds_bytes, stream);
 }
 
-int batch_workgroups_per_cu(bool discrete) {
+int batch_workgroups_per_cu(bool discrete, int lds_bytes) {
   const void* k = discrete ? reinterpret_cast<const void*>(&k_steps_batch<true>)
                            : reinterpret_cast<const void*>(&k_steps_batch<false>);
+  if (lds_bytes > 0 && hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes) != hipSuccess)
+    return 0;
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kThreads, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kThreads, (size_t)lds_bytes) != hipSuccess) return 0;
   return per_cu;
 }
 
