@@ -6,7 +6,8 @@ the eq. (1) energies) followed by gsb_best (argmin and its spins).  The instance
 synthetic stand-in for K2000 (Sec. III): J_ij iid uniform on {-1, +1}, generated from a
 seed, already resident in HBM when timing starts.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep] [--no-cpu] [--no-chaos]
+                    [--no-batch] [--no-dt]
 
 Prints one JSON line.
 """
@@ -138,6 +139,101 @@ def chaos_sweeps(J, c):
     return res
 
 
+def batched_uneven(seed: int = 1):
+    """Batched uneven instances in one persistent launch: 256 instances with n iid uniform
+    in [64, 4096], even indices dense +-1 (c = 1/(2 sqrt n), dt = 1.25, App. A), odd
+    indices Erdos-Renyi with p ~ U[0.01, 0.06] and +-1 weights (c = 1/lambda_max and
+    eq. (13) dt from the library's Lanczos estimate), 128 replicas each, 1000 steps of
+    GbSB (A = 0.2), FP8 product.  Tiles are autotuned on the device; the timed runs replay
+    one HIP graph (starting states, the persistent step kernel, energies and best)."""
+    import numpy as np
+    import torch
+
+    from paper_2508_17655_amd import gsb, instances
+
+    count, reps, steps, A = 256, 128, 1000, 0.2
+    specs = instances.batch_workload(count, seed)
+    t0 = time.perf_counter()
+    b = gsb.Batch([s_[1] for s_ in specs], reps)
+
+    def make(k):
+        J = instances.make_instance(specs[k])
+        return (J, instances.paper_c(specs[k][1]), 1.25) if specs[k][0] == "dense" else (J, 0.0, 0.0)
+
+    b.set_couplings(make, threads=16)
+    setup_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    b.autotune("gbsb", A=A, trial_steps=50, seed=1)
+    tune_s = time.perf_counter() - t0
+    b.run("gbsb", A=A, steps=steps, seed=seed)  # eager: the step kernel alone is timed
+    torch.cuda.synchronize()
+    kernel_ms = b.last_ms()
+    b.set(-1, gsb.GSB_BATCH_GRAPH, 1)
+    b.run("gbsb", A=A, steps=steps, seed=seed)  # capture
+    torch.cuda.synchronize()
+    graph_ms = []
+    for _ in range(3):
+        b.run("gbsb", A=A, steps=steps, seed=seed)
+        graph_ms.append(b.last_ms())
+    e_best, _ = b.best()
+    ns = np.array([s_[1] for s_ in specs], dtype=np.float64)
+    nps = np.ceil(ns / 512) * 512
+    tiles = np.array([b.get(k, gsb.GSB_BATCH_TILE_ROWS) for k in range(count)])
+    us = np.array([b.get(k, gsb.GSB_BATCH_STEP_US) for k in range(count)])
+    grid = b.get(-1, gsb.GSB_BATCH_GRID)
+    area_ms = float(np.sum(nps / tiles * (reps / (8192 / tiles)) * us * steps)) / grid / 1e3
+    b.close()
+    flop = 2.0 * float(np.sum(ns ** 2)) * reps * steps
+    gms = float(np.mean(graph_ms))
+    return {"workload": f"{count} instances, n iid U[64, 4096] (sum n = {int(ns.sum())}), half dense +-1, half "
+                        f"Erdos-Renyi p~U[0.01,0.06] +-1, {reps} replicas x {steps} steps, GbSB A={A}, FP8 product",
+            "value": float(ns.sum()) * reps * steps / (gms * 1e-3), "unit": "replica-spin-steps/s",
+            "ms_per_run": gms, "run": "HIP graph: starting states + persistent step kernel + energies + best",
+            "kernel_ms": kernel_ms,
+            "roofline": {"bound": "mfma", "achieved": flop / (kernel_ms * 1e-3) / 1e12, "peak": FP8_PEAK / 1e12,
+                         "unit": "TFLOP/s", "frac": flop / (kernel_ms * 1e-3) / FP8_PEAK,
+                         "flop_per_launch": flop, "kernel": "k_steps_batch (FP8 product, FP4 J rows in LDS)"},
+            "packing": {"ideal_ms": area_ms, "efficiency": area_ms / kernel_ms, "grid": int(grid)},
+            "tiles": {str(t): int(np.sum(tiles == t)) for t in (64, 128, 256)},
+            "setup_s": setup_s, "autotune_s": tune_s,
+            "best_energy_per_spin_mean": float(np.mean(e_best / ns))}
+
+
+def dt_study(J, c):
+    """Fig. 1(g, j) on the stand-in instance: P_S of GbSB (A = 0.2, 1024 replicas) and the
+    pair distance delta(t_M) (eq. (8), 64 pairs) over time steps dt and final times
+    t_M = dt M, in the 16-bit fixed-point form (the paper's JX precision; exact)."""
+    import numpy as np
+    import torch
+
+    from paper_2508_17655_amd import gsb
+
+    A = 0.2
+    dts = [0.5, 0.75, 1.0, 1.25]
+    t_ms = [1250.0, 2500.0, 5000.0, 10000.0, 25000.0]
+    g = gsb.GSB(J, precision="fix16", c=c)
+    gp = gsb.GSB(J, precision="fix16", c=c, init_mode=gsb.GSB_INIT_PAIRS)
+    rows = []
+    t0 = time.perf_counter()
+    for dt in dts:
+        for tm in t_ms:
+            M = int(round(tm / dt))
+            g.run("gbsb", A=A, dt=dt, replicas=R, steps=M, seed=7000)
+            E = g.energy()
+            gp.run("gbsb", A=A, dt=dt, replicas=128, steps=M, seed=7001)
+            rows.append({"dt": dt, "t_M": tm, "M": M, "E": E, "delta": float(np.mean(gp.delta()))})
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    g.close()
+    gp.close()
+    e_star = min(float(r["E"].min()) for r in rows)
+    for r in rows:
+        E = r.pop("E")
+        r["p_hat"] = float(np.mean(E == e_star))
+        r["best"] = float(E.min())
+    return {"A": A, "form": "fix16", "replicas": R, "pairs": 64, "e_star": e_star, "s": wall, "table": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +242,8 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the P_S/TTS99 sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-chaos", action="store_true", help="skip the LLE and delta sweeps")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven-instance workload")
+    ap.add_argument("--no-dt", action="store_true", help="skip the time-step study")
     ap.add_argument("--profile", action="store_true", help="few untimed runs only (for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -283,6 +381,10 @@ def main():
         out["tts99_s"] = best_row["fp8"]["tts99_s"]
     if not args.no_chaos:
         out["chaos"] = chaos_sweeps(J, c)
+    if not args.no_batch:
+        out["batched"] = batched_uneven()
+    if not args.no_dt:
+        out["dt_study"] = dt_study(J, c)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(J.astype(np.float64), c)
     print(json.dumps(out))

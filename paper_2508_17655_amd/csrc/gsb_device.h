@@ -17,9 +17,11 @@ typedef unsigned v2u __attribute__((ext_vector_type(2)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
-// Cache policy of operand loads: plain (L1 and L2 cacheable).  Every barrier that
-// publishes an operand buffer invalidates the reader CU's L1 (group_sync), so no stale
-// line survives; device-scope loads instead go past L2 and cost ~1.5 us each.
+// Cache policies of operand loads.  Device scope skips L1, so the operand, which no two
+// waves of a workgroup share, does not evict the J lines they do share.  Plain loads may
+// hit L1; every barrier that publishes an operand buffer invalidates the reader CU's L1
+// (group_sync), so no stale line survives either way.
+constexpr int kPolicySc1 = 16;
 constexpr int kPolicyPlain = 0;
 constexpr unsigned kSpinLimit = 1u << 22;  // polls before a barrier gives up (seconds)
 constexpr int kHwRegXccId = 20 | (0 << 6) | ((4 - 1) << 11);  // hwreg(HW_REG_XCC_ID, 0, 4)

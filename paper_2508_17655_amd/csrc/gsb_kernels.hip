@@ -36,7 +36,7 @@ __device__ __forceinline__ void gemm_tile_fp32(const uint8_t* jrows, __amdgpu_bu
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct) {
         const unsigned base = (unsigned)(((size_t)((rb0 + ct) * nks + ks) * 8 + grp) * 1024 + lane * 16);
-        bq[ct] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kPolicyPlain));
+        bq[ct] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kPolicySc1));
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t)
@@ -80,7 +80,9 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
   static_assert(BM == 64 || BM == 128 || BM == 256, "tile rows");
   constexpr int BN = 8192 / BM;
   constexpr int WCOLS = BN / kWaveCols;  // waves across the replica columns
-  constexpr int kQPolicy = kPolicyPlain;  // L1 is invalidated at every barrier
+  // with J in L1 (read by the waves of a workgroup) the operand skips L1; with J in LDS
+  // it may use L1
+  constexpr int kQPolicy = LJ ? kPolicyPlain : kPolicySc1;
 
   // the wave index is uniform within a wave; readfirstlane tells the compiler so
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -261,7 +263,7 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct) {
               const unsigned base = (unsigned)(pl * plane_bytes + ((size_t)((rb0 + ct) * nks + ks) * 4 + sub) * 1024 + lane * 16);
-              bq[ct] = __builtin_bit_cast(v8bf, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kPolicyPlain));
+              bq[ct] = __builtin_bit_cast(v8bf, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kQPolicy));
             }
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt)
@@ -273,8 +275,12 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
       }
     } else if constexpr (FORM == kFormFIX16) {
       // two int8 passes (hi, lo planes; the sign operand has lo = 0), exact int32 sums;
-      // G = 256 G_hi + G_lo is exact in int32 and rounded to binary32 once, then scaled
+      // G = 256 G_hi + G_lo is exact in int32 and rounded to binary32 once, then scaled.
+      // Software pipeline over half k-steps (64 spins): Q fragments of both planes are
+      // fetched kPFs half-steps ahead and J fragments one ahead.  2 nks is a multiple of
+      // kPFs; the last kPFs half-steps are peeled without loads.
       constexpr int planes = DISC ? 1 : 2;
+      constexpr int kPFs = kKStepsUnroll;
       v4i iacc[2][4][2];
 #pragma unroll
       for (int pl = 0; pl < 2; ++pl)
@@ -282,29 +288,54 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
         for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
           for (int ct = 0; ct < 2; ++ct) iacc[pl][rt][ct] = v4i{0, 0, 0, 0};
-      for (int ks = 0; ks < nks; ++ks) {
+      const int nsub = 2 * nks;
+      v4i aj[2][4];
+      v4i bq[kPFs][planes][2];
+      auto load_a = [&](int sb, v4i* dst) {
 #pragma unroll
-        for (int half = 0; half < 2; ++half) {
-          v4i aj[4];
+        for (int rt = 0; rt < 4; ++rt)
+          dst[rt] = *reinterpret_cast<const v4i*>(jrows + ((size_t)(rt * nks + (sb >> 1)) * 2 + (sb & 1)) * 1024 +
+                                                  lane * 16);
+      };
+      auto load_b = [&](int sb, v4i (*dst)[2]) {
+#pragma unroll
+        for (int pl = 0; pl < planes; ++pl)
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) {
+            const unsigned base = (unsigned)(pl * plane_bytes + ((size_t)((rb0 + ct) * nks + (sb >> 1)) * 2 + (sb & 1)) *
+                                                                    1024 + lane * 16);
+            dst[pl][ct] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kQPolicy));
+          }
+      };
+      auto mfmas = [&](const v4i* aa, v4i (*bb)[2]) {
+#pragma unroll
+        for (int pl = 0; pl < planes; ++pl)
 #pragma unroll
           for (int rt = 0; rt < 4; ++rt)
-            aj[rt] = *reinterpret_cast<const v4i*>(jrows + ((size_t)(rt * nks + ks) * 2 + half) * 1024 + lane * 16);
 #pragma unroll
-          for (int pl = 0; pl < planes; ++pl) {
-            v4i bq[2];
+            for (int ct = 0; ct < 2; ++ct)
+              iacc[pl][rt][ct] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aa[rt], bb[pl][ct], iacc[pl][rt][ct], 0, 0, 0);
+      };
 #pragma unroll
-            for (int ct = 0; ct < 2; ++ct) {
-              const unsigned base =
-                  (unsigned)(pl * plane_bytes + ((size_t)((rb0 + ct) * nks + ks) * 2 + half) * 1024 + lane * 16);
-              bq[ct] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kPolicyPlain));
-            }
+      for (int u = 0; u < kPFs; ++u) load_b(u, bq[u]);
+      load_a(0, aj[0]);
+      int s0 = 0;
+      for (; s0 < nsub - kPFs; s0 += kPFs) {
 #pragma unroll
-            for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-              for (int ct = 0; ct < 2; ++ct)
-                iacc[pl][rt][ct] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aj[rt], bq[ct], iacc[pl][rt][ct], 0, 0, 0);
-          }
+        for (int u = 0; u < kPFs; ++u) {
+          load_a(s0 + u + 1, aj[(u + 1) & 1]);
+          __builtin_amdgcn_sched_barrier(0);
+          mfmas(aj[u & 1], bq[u]);
+          load_b(s0 + u + kPFs, bq[u]);
+          __builtin_amdgcn_sched_barrier(0);
         }
+      }
+#pragma unroll
+      for (int u = 0; u < kPFs; ++u) {
+        if (u + 1 < kPFs) load_a(s0 + u + 1, aj[(u + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+        mfmas(aj[u & 1], bq[u]);
+        __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int rt = 0; rt < 4; ++rt)

@@ -41,7 +41,8 @@ __global__ void __launch_bounds__(kThreads, 1) __attribute__((amdgpu_waves_per_e
   constexpr int NACC = NKS > kAccKSteps ? kAccKSteps : NKS;
   constexpr int NVJ = NKS - NACC;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the wave index is uniform within a wave; readfirstlane tells the compiler so
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = blockIdx.x % a.groups;
   const int mb = blockIdx.x / a.groups;
   const int row0 = mb * 256 + wave * kWaveRows;
