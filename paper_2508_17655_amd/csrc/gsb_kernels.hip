@@ -15,6 +15,7 @@
 #include "gsb_device.h"
 
 #include <algorithm>
+#include <type_traits>
 
 #pragma clang fp contract(off)
 
@@ -183,16 +184,15 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
       for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 
     if constexpr (FORM == kFormFP8) {
-      // Software pipeline: Q fragments are fetched kPF k-steps ahead and FP4 J fragments
-      // one k-step ahead, so neither latency stalls the MFMA stream.  The k-steps run in
-      // two segments, [0, nks_l) with J from LDS and [nks_l, nks) with J from L2, each a
-      // pipeline of its own: J registers are then never written by an LDS read while a
-      // global load to them may be in flight (which would force a full wait).  Segment
-      // lengths are multiples of kPF; each prefetches unconditionally and peels its last
-      // kPF k-steps without loads.
+      // Software pipeline: Q fragments are fetched kPF k-steps ahead, FP4 J fragments one
+      // k-step ahead from LDS or kPF - 1 ahead from L2/MALL, so no latency stalls the
+      // MFMA stream.  The k-steps run in two segments, [0, nks_l) with J from LDS and
+      // [nks_l, nks) with J from L2, each a pipeline of its own: J registers are then
+      // never written by an LDS read while a global load to them may be in flight (which
+      // would force a full wait).  Segment lengths are multiples of kPF; the last kPF
+      // k-steps of each are peeled without Q loads.
       constexpr int kPF = kKStepsUnroll;
       v8i bq[kPF][2];
-      v4i aj[2][4];
       auto load_b = [&](int ks, v8i* dst) {
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
@@ -220,33 +220,40 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
             acc[rt][ct] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(cat(aa[rt], aa[rt]), bb[ct], acc[rt][ct],
                                                                            4, 0, 0, 127, 0, 127);
       };
-      auto segment = [&](int k0, int k1, auto load_a) {
+      // JD: J prefetch distance (1 or kPF - 1), in a ring of JD + 1 register sets that
+      // divides kPF, so every ring index is a compile-time constant
+      auto segment = [&](int k0, int k1, auto load_a, auto jd) {
+        constexpr int JD = decltype(jd)::value;
+        constexpr int RING = JD + 1;
+        static_assert(kPF % RING == 0, "J ring must divide the unroll");
+        v4i aj[RING][4];
 #pragma unroll
         for (int u = 0; u < kPF; ++u) load_b(k0 + u, bq[u]);
-        load_a(k0, aj[0]);
+#pragma unroll
+        for (int d = 0; d < JD; ++d) load_a(k0 + d, aj[d]);  // segments hold >= kPF > JD k-steps
         int ks0 = k0;
         for (; ks0 < k1 - kPF; ks0 += kPF) {
 #pragma unroll
           for (int u = 0; u < kPF; ++u) {
-            load_a(ks0 + u + 1, aj[(u + 1) & 1]);
-            __builtin_amdgcn_sched_barrier(0);  // keep each prefetch ahead of the MFMAs
-            mfmas(aj[u & 1], bq[u]);
+            load_a(ks0 + u + JD, aj[(u + JD) % RING]);  // < k1: ks0 + kPF <= k1 - kPF
+            __builtin_amdgcn_sched_barrier(0);          // keep each prefetch ahead of the MFMAs
+            mfmas(aj[u % RING], bq[u]);
             load_b(ks0 + u + kPF, bq[u]);
             __builtin_amdgcn_sched_barrier(0);
           }
         }
 #pragma unroll
         for (int u = 0; u < kPF; ++u) {
-          if (u + 1 < kPF) load_a(ks0 + u + 1, aj[(u + 1) & 1]);
+          if (u + JD < kPF) load_a(ks0 + u + JD, aj[(u + JD) % RING]);
           __builtin_amdgcn_sched_barrier(0);
-          mfmas(aj[u & 1], bq[u]);
+          mfmas(aj[u % RING], bq[u]);
           __builtin_amdgcn_sched_barrier(0);
         }
       };
       if constexpr (LJ) {
-        if (nks_l > 0) segment(0, nks_l, load_a_lds);
+        if (nks_l > 0) segment(0, nks_l, load_a_lds, std::integral_constant<int, 1>{});
       }
-      if (nks_l < nks) segment(nks_l, nks, load_a_glb);
+      if (nks_l < nks) segment(nks_l, nks, load_a_glb, std::integral_constant<int, kPF - 1>{});
     } else if constexpr (FORM == kFormBF16X2) {
       constexpr int planes = DISC ? 1 : 2;  // sgn(x) has no low part
       for (int ks = 0; ks < nks; ++ks) {
