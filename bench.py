@@ -139,6 +139,24 @@ def chaos_sweeps(J, c):
     return res
 
 
+BATCH_COUNT, BATCH_R, BATCH_M, BATCH_A = 256, 128, 1000, 0.2
+
+
+def batched_setup(specs):
+    """A Batch holding every instance of `specs`: dense +-1 with c = 1/(2 sqrt n), dt = 1.25
+    (App. A); sparse with c and dt from the library (App. A, eq. (13))."""
+    from paper_2508_17655_amd import gsb, instances
+
+    b = gsb.Batch([s_[1] for s_ in specs], BATCH_R)
+
+    def make(k):
+        J = instances.make_instance(specs[k])
+        return (J, instances.paper_c(specs[k][1]), 1.25) if specs[k][0] == "dense" else (J, 0.0, 0.0)
+
+    b.set_couplings(make, threads=16)
+    return b
+
+
 def batched_uneven(seed: int = 1):
     """Batched uneven instances in one persistent launch: 256 instances with n iid uniform
     in [64, 4096], even indices dense +-1 (c = 1/(2 sqrt n), dt = 1.25, App. A), odd
@@ -151,16 +169,10 @@ def batched_uneven(seed: int = 1):
 
     from paper_2508_17655_amd import gsb, instances
 
-    count, reps, steps, A = 256, 128, 1000, 0.2
+    count, reps, steps, A = BATCH_COUNT, BATCH_R, BATCH_M, BATCH_A
     specs = instances.batch_workload(count, seed)
     t0 = time.perf_counter()
-    b = gsb.Batch([s_[1] for s_ in specs], reps)
-
-    def make(k):
-        J = instances.make_instance(specs[k])
-        return (J, instances.paper_c(specs[k][1]), 1.25) if specs[k][0] == "dense" else (J, 0.0, 0.0)
-
-    b.set_couplings(make, threads=16)
+    b = batched_setup(specs)
     setup_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     b.autotune("gbsb", A=A, trial_steps=50, seed=1)
@@ -245,6 +257,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven-instance workload")
     ap.add_argument("--no-dt", action="store_true", help="skip the time-step study")
     ap.add_argument("--profile", action="store_true", help="few untimed runs only (for rocprofv3)")
+    ap.add_argument("--profile-batch", action="store_true",
+                    help="the batched workload, autotuned, then two untimed runs (for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path (replicas would shard "
@@ -257,6 +271,15 @@ def main():
     from paper_2508_17655_amd import gsb, instances
 
     torch.cuda.set_device(0)
+    if args.profile_batch:
+        b = batched_setup(instances.batch_workload(BATCH_COUNT, 1))
+        b.autotune("gbsb", A=BATCH_A, trial_steps=50, seed=1)
+        for s in range(2):
+            b.run("gbsb", A=BATCH_A, steps=BATCH_M, seed=1 + s)
+        torch.cuda.synchronize()
+        b.close()
+        print(json.dumps({"profile_runs": 2, "batch": BATCH_COUNT}))
+        return
     J = instances.dense_pm1(N, SEED_J)
     c = instances.paper_c(N)
     g8 = gsb.GSB(J, precision="fp8", c=c)
