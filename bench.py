@@ -211,6 +211,39 @@ def batched_uneven(seed: int = 1):
             "best_energy_per_spin_mean": float(np.mean(e_best / ns))}
 
 
+def precision_forms(J, c):
+    """The precision workload at 4096 replicas x 2000 steps: sign products (dSB, GdSB) and
+    GbSB in the FP8 form, bSB and GbSB in the BF16X2 form, and a real-weighted instance
+    (J_ij ~ N(0,1)/sqrt(N), BF16 J, BF16X2 x) with c = 1/lambda_max and eq. (13) dt.
+    Throughput and fraction of the dense peak of the step launch (HIP events)."""
+    import numpy as np
+
+    from paper_2508_17655_amd import gsb, instances
+
+    reps, steps = 4096, 2000
+    flop = 2.0 * N * N * reps * steps
+    out = []
+    Jg = instances.dense_gaussian(N, 3)
+    cases = [("dsb", "fp8", J, c, DT), ("gdsb", "fp8", J, c, DT), ("gbsb", "fp8", J, c, DT),
+             ("bsb", "bf16x2", J, c, DT), ("gbsb", "bf16x2", J, c, DT), ("gbsb", "bf16x2 (real J)", Jg, None, None)]
+    for variant, form, JJ, cc, dt in cases:
+        g = gsb.GSB(JJ, precision=form.split()[0], c=cc)
+        if dt is None:
+            dt = g.get(gsb.GSB_OPT_DT_STABLE)
+        g.run(variant, A=A_HEAD, dt=dt, replicas=reps, steps=steps, seed=1)
+        g.run(variant, A=A_HEAD, dt=dt, replicas=reps, steps=steps, seed=2)
+        ms = g.last_step_ms()
+        E = g.energy()
+        g.close()
+        peak, executed = (FP8_PEAK, flop) if form == "fp8" else (2.5e15, 2 * flop)  # BF16X2: two passes
+        out.append({"variant": variant, "form": form, "kernel_ms": ms, "value": N * reps * steps / (ms * 1e-3),
+                    "unit": "replica-spin-steps/s", "peak_frac": executed / (ms * 1e-3) / peak,
+                    "best": float(E.min()), "dt": dt})
+    return {"replicas": reps, "steps": steps, "n": N, "A": A_HEAD, "rows": out,
+            "errors": "stated by tests: sign/E4M3 forms bit-exact; BF16X2 one step within 1e-5 (+-1 J) and "
+                      "dy within 4e-3 (real J, bf16-rounded couplings) of binary64"}
+
+
 def dt_study(J, c):
     """Fig. 1(g, j) on the stand-in instance: P_S of GbSB (A = 0.2, 1024 replicas) and the
     pair distance delta(t_M) (eq. (8), 64 pairs) over time steps dt and final times
@@ -256,6 +289,7 @@ def main():
     ap.add_argument("--no-chaos", action="store_true", help="skip the LLE and delta sweeps")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched uneven-instance workload")
     ap.add_argument("--no-dt", action="store_true", help="skip the time-step study")
+    ap.add_argument("--no-precision", action="store_true", help="skip the 4096-replica precision workload")
     ap.add_argument("--profile", action="store_true", help="few untimed runs only (for rocprofv3)")
     ap.add_argument("--profile-batch", action="store_true",
                     help="the batched workload, autotuned, then two untimed runs (for rocprofv3)")
@@ -408,6 +442,8 @@ def main():
         out["batched"] = batched_uneven()
     if not args.no_dt:
         out["dt_study"] = dt_study(J, c)
+    if not args.no_precision:
+        out["precision"] = precision_forms(J, c)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(J.astype(np.float64), c)
     print(json.dumps(out))

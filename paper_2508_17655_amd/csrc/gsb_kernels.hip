@@ -255,30 +255,60 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
       }
       if (nks_l < nks) segment(nks_l, nks, load_a_glb, std::integral_constant<int, kPF - 1>{});
     } else if constexpr (FORM == kFormBF16X2) {
-      constexpr int planes = DISC ? 1 : 2;  // sgn(x) has no low part
-      for (int ks = 0; ks < nks; ++ks) {
+      // hi and lo planes of x (the sign operand has no low part) against bf16 J, 16x16x32
+      // MFMAs with binary32 accumulation.  Software pipeline over quarter k-steps (32
+      // spins): Q fragments of both planes kPFs quarters ahead, J fragments one ahead;
+      // 4 nks is a multiple of kPFs and the last kPFs quarters are peeled without loads.
+      constexpr int planes = DISC ? 1 : 2;
+      constexpr int kPFs = kKStepsUnroll;
+      const int nsub = 4 * nks;
+      v8bf aj[2][4];
+      v8bf bq[kPFs][planes][2];
+      auto load_a = [&](int sb, v8bf* dst) {
 #pragma unroll
-        for (int sub = 0; sub < 4; ++sub) {
-          v8bf aj[4];
+        for (int rt = 0; rt < 4; ++rt)
+          dst[rt] = *reinterpret_cast<const v8bf*>(jrows + ((size_t)(rt * nks + (sb >> 2)) * 4 + (sb & 3)) * 1024 +
+                                                   lane * 16);
+      };
+      auto load_b = [&](int sb, v8bf (*dst)[2]) {
 #pragma unroll
-          for (int rt = 0; rt < 4; ++rt) {
-            const size_t o = ((size_t)(rt * nks + ks) * 4 + sub) * 1024 + lane * 16;
-            aj[rt] = *reinterpret_cast<const v8bf*>(jrows + o);
+        for (int pl = 0; pl < planes; ++pl)
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) {
+            const unsigned base = (unsigned)(pl * plane_bytes + ((size_t)((rb0 + ct) * nks + (sb >> 2)) * 4 + (sb & 3)) *
+                                                                    1024 + lane * 16);
+            dst[pl][ct] = __builtin_bit_cast(v8bf, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kQPolicy));
           }
-          for (int pl = 0; pl < planes; ++pl) {
-            v8bf bq[2];
+      };
+      auto mfmas = [&](const v8bf* aa, v8bf (*bb)[2]) {
 #pragma unroll
-            for (int ct = 0; ct < 2; ++ct) {
-              const unsigned base = (unsigned)(pl * plane_bytes + ((size_t)((rb0 + ct) * nks + ks) * 4 + sub) * 1024 + lane * 16);
-              bq[ct] = __builtin_bit_cast(v8bf, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kQPolicy));
-            }
+        for (int pl = 0; pl < planes; ++pl)
 #pragma unroll
-            for (int rt = 0; rt < 4; ++rt)
+          for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-              for (int ct = 0; ct < 2; ++ct)
-                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aj[rt], bq[ct], acc[rt][ct], 0, 0, 0);
-          }
+            for (int ct = 0; ct < 2; ++ct)
+              acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aa[rt], bb[pl][ct], acc[rt][ct], 0, 0, 0);
+      };
+#pragma unroll
+      for (int u = 0; u < kPFs; ++u) load_b(u, bq[u]);
+      load_a(0, aj[0]);
+      int s0 = 0;
+      for (; s0 < nsub - kPFs; s0 += kPFs) {
+#pragma unroll
+        for (int u = 0; u < kPFs; ++u) {
+          load_a(s0 + u + 1, aj[(u + 1) & 1]);
+          __builtin_amdgcn_sched_barrier(0);
+          mfmas(aj[u & 1], bq[u]);
+          load_b(s0 + u + kPFs, bq[u]);
+          __builtin_amdgcn_sched_barrier(0);
         }
+      }
+#pragma unroll
+      for (int u = 0; u < kPFs; ++u) {
+        if (u + 1 < kPFs) load_a(s0 + u + 1, aj[(u + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+        mfmas(aj[u & 1], bq[u]);
+        __builtin_amdgcn_sched_barrier(0);
       }
     } else if constexpr (FORM == kFormFIX16) {
       // two int8 passes (hi, lo planes; the sign operand has lo = 0), exact int32 sums;

@@ -240,6 +240,35 @@ def test_real_weighted_energy_fp64(orc):
     np.testing.assert_allclose(E, Eo, rtol=1e-13, atol=1e-12)
 
 
+def test_real_weighted_bf16_one_step_error(orc):
+    # J_ij ~ N(0,1)/sqrt(N) in the BF16X2 form: J itself is rounded to bf16 (relative
+    # error <= 2^-9 per coupling, random in sign), x is split hi/lo.  One step from an
+    # identical state against the binary64 step with the exact J: the coupling increment
+    # dy = y' - y (c dt J x, minus the small p x dt term) is off by about 2^-9 / sqrt(3)
+    # relative; bound 4e-3.
+    n, R, M, seed = 2000, 128, 2000, 6
+    say(f"case real-weighted bf16 one step n={n}")
+    J = instances.dense_gaussian(n, 3)
+    g = gsb.GSB(J)  # default precision for real J: BF16X2
+    c = g.get(gsb.GSB_OPT_C)
+    dt = g.get(gsb.GSB_OPT_DT_STABLE)
+    g.init("gbsb", A=0.2, dt=dt, replicas=R, steps=M, seed=seed)
+    samp = np.arange(4)
+    x0, y0, p0 = oracle_start(orc, n, R, seed, orc.INIT_X)
+    kw = dict(A=0.2, dt=dt, c=c, steps=M)
+    xs, ys, ps = orc.run(J, orc.GBSB, x=x0, y=y0, p=p0, m_end=40, mode="fp64", **kw)
+    xs, ys, ps = (v.astype(np.float32) for v in (xs, ys, ps))
+    g.set_state(xs, ys, ps, 40)
+    g.step(1)
+    yg = g.state()[1][samp]
+    g.close()
+    y64 = orc.run(J, orc.GBSB, x=xs[samp], y=ys[samp], p=ps[samp], m_begin=40, m_end=41, mode="fp64", **kw)[1]
+    d64 = y64 - ys[samp]
+    rel = np.linalg.norm((yg - ys[samp]) - d64, axis=1) / np.linalg.norm(d64, axis=1)
+    say(f"  one-step relative error of dy: {rel.max():.3e}")
+    assert rel.max() <= 4e-3
+
+
 def test_field_ancilla_energy(orc):
     n, R, M = 40, 128, 300
     say(f"case field n={n}")
