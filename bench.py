@@ -193,6 +193,7 @@ def batched_uneven(seed: int = 1):
     tiles = np.array([b.get(k, gsb.GSB_BATCH_TILE_ROWS) for k in range(count)])
     us = np.array([b.get(k, gsb.GSB_BATCH_STEP_US) for k in range(count)])
     grid = b.get(-1, gsb.GSB_BATCH_GRID)
+    occupancy = int(b.get(-1, gsb.GSB_BATCH_OCCUPANCY))
     area_ms = float(np.sum(nps / tiles * (reps / (8192 / tiles)) * us * steps)) / grid / 1e3
     b.close()
     flop = 2.0 * float(np.sum(ns ** 2)) * reps * steps
@@ -205,7 +206,8 @@ def batched_uneven(seed: int = 1):
             "roofline": {"bound": "mfma", "achieved": flop / (kernel_ms * 1e-3) / 1e12, "peak": FP8_PEAK / 1e12,
                          "unit": "TFLOP/s", "frac": flop / (kernel_ms * 1e-3) / FP8_PEAK,
                          "flop_per_launch": flop, "kernel": "k_steps_batch (FP8 product, FP4 J rows in LDS)"},
-            "packing": {"ideal_ms": area_ms, "efficiency": area_ms / kernel_ms, "grid": int(grid)},
+            "packing": {"ideal_ms": area_ms, "efficiency": area_ms / kernel_ms, "grid": int(grid),
+                        "workgroups_per_cu": occupancy},
             "tiles": {str(t): int(np.sum(tiles == t)) for t in (64, 128, 256)},
             "setup_s": setup_s, "autotune_s": tune_s,
             "best_energy_per_spin_mean": float(np.mean(e_best / ns))}

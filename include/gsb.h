@@ -274,7 +274,11 @@ typedef enum {
   GSB_BATCH_INIT_MODE = 8,  /* batch-wide (k = -1): gsb_init_mode (default GSB_INIT_X) */
   GSB_BATCH_COUNT = 9,      /* batch-wide, read-only: count */
   GSB_BATCH_REPLICAS = 10,  /* batch-wide, read-only: replicas */
-  GSB_BATCH_GRID = 11       /* batch-wide, read-only: workgroups of the persistent launch */
+  GSB_BATCH_GRID = 11,      /* batch-wide, read-only: workgroups of the persistent launch */
+  GSB_BATCH_OCCUPANCY = 12  /* batch-wide: workgroups per CU of the launch, 1 or 2 (with 2, one
+                               workgroup's update and barrier overlap the other's product,
+                               with half the LDS and a shallower prefetch each); 0 (default) =
+                               chosen by gsb_batch_autotune, 1 until it runs */
 } gsb_batch_option;
 
 /* Create a batch of `count` instances (1 <= count <= 65536) of sizes n[k]
@@ -315,9 +319,11 @@ gsb_status gsb_batch_set(gsb_batch* batch, int32_t k, int32_t option, double val
 gsb_status gsb_batch_get(gsb_batch* batch, int32_t k, int32_t option, double* value);
 
 /* Measure, on the device, the step time of every instance at each tile shape (64, 128
- * and 256 rows; shapes whose gang does not fit in one XCD are skipped) with trial runs of
- * `trial_steps` steps of the whole batch, and keep the results for later runs (tile
- * choice and queue balance).  Instances with a fixed GSB_BATCH_TILE_ROWS keep it.
+ * and 256 rows; shapes whose gang does not fit in one XCD are skipped) and each
+ * occupancy (1 and 2 workgroups per CU) with trial runs of `trial_steps` steps of the
+ * whole batch, keep the results for later runs (tile choice and queue balance), and
+ * choose the occupancy whose whole-batch trial with its fastest tiles is quicker.
+ * Instances with a fixed GSB_BATCH_TILE_ROWS keep it, a fixed GSB_BATCH_OCCUPANCY too.
  * Leaves no current run.  Synchronises.  Errors: EINVAL, ESTATE, EUNSUPPORTED, EDEVICE. */
 gsb_status gsb_batch_autotune(gsb_batch* batch, int32_t variant, double control_strength, int32_t trial_steps,
                               uint64_t seed);

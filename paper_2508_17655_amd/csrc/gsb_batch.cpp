@@ -81,7 +81,9 @@ struct gsb_batch {
   std::vector<double> c, dt, lmax, lmin;
   std::vector<char> have_j, have_eig;
   std::vector<int> tile_fixed;             // 0: automatic
-  std::vector<double> us[3];               // measured us per step of one gang, per tile
+  std::vector<double> us[2][3];            // measured us per step of one gang, per occupancy and tile
+  int occ = 1;                             // workgroups per CU of the runs (1 or 2)
+  int occ_fixed = 0;                       // caller's choice, 0 = automatic
   int init_mode = GSB_INIT_X;
   bool use_graph = false;
   hipStream_t stream = nullptr;
@@ -111,7 +113,9 @@ struct gsb_batch {
   float* d_rtab = nullptr;
   unsigned long long* d_clk = nullptr;
   // device facts
-  int per_cu = 0, grid = 0, cap = 0, lds_bytes = 0;
+  // per occupancy (index occ - 1): workgroups of the launch, per XCD queue, LDS for J rows
+  int grid[2] = {0, 0}, cap[2] = {0, 0}, lds_bytes[2] = {0, 0};
+  bool facts = false;
   double wall_hz = 0;
   // run
   bool ran = false;
@@ -129,7 +133,7 @@ struct gsb_batch {
 namespace {
 
 gsb_status device_facts(gsb_batch* b) {
-  if (b->grid) return GSB_OK;
+  if (b->facts) return GSB_OK;
   int dev = 0, cus = 0, rate_khz = 0, lds_max = 0;
   BHIP(hipGetDevice(&dev), "hipGetDevice");
   BHIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "device attribute");
@@ -137,12 +141,18 @@ gsb_status device_facts(gsb_batch* b) {
   BHIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "device attribute");
   // the step kernel runs one workgroup per CU (registers), so J rows may fill the LDS
   // beside the kernel's own few bytes
-  b->lds_bytes = std::max(0, std::min(lds_max, 160 * 1024) - 1024) / 1024 * 1024;
-  const int a = batch_workgroups_per_cu(false, b->lds_bytes), d = batch_workgroups_per_cu(true, b->lds_bytes);
-  b->per_cu = std::min(a, d);
-  if (b->per_cu < 1) return bfail(GSB_EDEVICE, "occupancy query failed for the batched step kernel");
-  b->grid = b->per_cu * cus;
-  b->cap = b->grid / kBatchXcds;
+  for (int occ = 1; occ <= 2; ++occ) {
+    const int lds = std::max(0, std::min(lds_max, 160 * 1024) / occ - 1024) / 1024 * 1024;
+    const int a = batch_workgroups_per_cu(false, occ, lds), d = batch_workgroups_per_cu(true, occ, lds);
+    const int per_cu = std::min(std::min(a, d), occ);
+    if (per_cu < 1) return bfail(GSB_EDEVICE, "occupancy query failed for the batched step kernel");
+    b->lds_bytes[occ - 1] = lds;
+    b->grid[occ - 1] = per_cu * cus;
+    b->cap[occ - 1] = b->grid[occ - 1] / kBatchXcds;
+  }
+  // occupancy 2 only where the hardware gives it
+  if (b->grid[1] < 2 * b->grid[0]) b->grid[1] = 0;
+  b->facts = true;
   b->wall_hz = rate_khz > 0 ? rate_khz * 1e3 : 1e8;
   return GSB_OK;
 }
@@ -202,17 +212,18 @@ void drop_graph(gsb_batch* b) {
 
 // Tile rows of instance k: the caller's choice, else the fastest measured tile, else the
 // smallest tile whose gang fits in one XCD queue.
-int choose_tile(const gsb_batch* b, int k) {
+int choose_tile(const gsb_batch* b, int k, int occ) {
+  const int cap = b->cap[occ - 1];
   if (b->tile_fixed[k]) return b->tile_fixed[k];
   int best = 0;
   double best_us = 0;
   for (int t = 0; t < 3; ++t) {
-    const double u = b->us[t][k];
-    if (u > 0 && b->np[k] / kTiles[t] <= b->cap && (best == 0 || u < best_us)) { best = kTiles[t]; best_us = u; }
+    const double u = b->us[occ - 1][t][k];
+    if (u > 0 && b->np[k] / kTiles[t] <= cap && (best == 0 || u < best_us)) { best = kTiles[t]; best_us = u; }
   }
   if (best) return best;
   for (int t = 0; t < 3; ++t)
-    if (b->np[k] / kTiles[t] <= b->cap) return kTiles[t];
+    if (b->np[k] / kTiles[t] <= cap) return kTiles[t];
   return 0;
 }
 
@@ -247,17 +258,18 @@ gsb_status prepare(gsb_batch* b, int variant, double A, int steps, uint64_t seed
   std::vector<int> width(b->count), gangs(b->count), queue(b->count), rank(b->count);
   std::vector<double> cost(b->count);
   for (int k = 0; k < b->count; ++k) {
-    const int bm = tile_override ? tile_override[k] : choose_tile(b, k);
-    if (bm == 0 || b->np[k] / bm > b->cap)
+    const int bm = tile_override ? tile_override[k] : choose_tile(b, k, b->occ);
+    if (bm == 0 || b->np[k] / bm > b->cap[b->occ - 1])
       return bfail(GSB_EUNSUPPORTED, "instance " + std::to_string(k) + " (n = " + std::to_string(b->n[k]) +
                                          ") does not fit in the workgroups of one XCD");
     b->h_tile[k] = bm;
     width[k] = b->np[k] / bm;
     gangs[k] = b->rp / (8192 / bm);
-    const double u = b->us[tile_index(bm)][k];
+    const double u = b->us[b->occ - 1][tile_index(bm)][k];
     cost[k] = u > 0 ? u : 1.0 + 1.2e-3 * b->np[k];  // unmeasured: a model of us per step
   }
-  s = plan_queues(b->count, width.data(), gangs.data(), cost.data(), kBatchXcds, b->cap, queue.data(), rank.data());
+  s = plan_queues(b->count, width.data(), gangs.data(), cost.data(), kBatchXcds, b->cap[b->occ - 1], queue.data(),
+                  rank.data());
   if (s != GSB_OK) return s;
   // slots: per XCD queue in rank order, then the device-wide queue in decreasing cost
   b->h_slots.clear();
@@ -314,7 +326,6 @@ gsb_status prepare(gsb_batch* b, int variant, double A, int steps, uint64_t seed
     BHIP(launch_fill_u32(reinterpret_cast<unsigned*>(b->d_clk), 4 * nslots, 0u, b->stream), "clear clocks");
   for (int k = 0; k < b->count; ++k) {
     StepArgs& a = b->h_inst[k];
-    const int bm = b->h_tile[k];
     a.n = b->n[k];
     a.np = b->np[k];
     a.rp = b->rp;
@@ -336,7 +347,6 @@ gsb_status prepare(gsb_batch* b, int variant, double A, int steps, uint64_t seed
     a.p = reinterpret_cast<float*>(w + b->off_p[k]);
     a.sync = reinterpret_cast<unsigned*>(w + b->off_sync[k]);
     a.status = reinterpret_cast<unsigned*>(w + b->off_status);
-    (void)bm;
     BatchInst& bi = b->h_bi[k];
     bi.seed = seed + (uint64_t)k;
     bi.s8 = w + b->off_s8[k];
@@ -379,10 +389,10 @@ gsb_status enqueue_run(gsb_batch* b, bool discrete, bool cooperative, bool timed
   a.ctl = reinterpret_cast<unsigned*>(w + b->off_ctl);
   a.status = reinterpret_cast<unsigned*>(w + b->off_status);
   a.clk = b->d_clk;
-  a.grid = b->grid;
-  a.lds_bytes = b->lds_bytes;
+  a.grid = b->grid[b->occ - 1];
+  a.lds_bytes = b->lds_bytes[b->occ - 1];
   if (timed) BHIP(hipEventRecord(b->ev0, st), "event record");
-  BHIP(launch_steps_batch(discrete, a, st, cooperative), "batched step kernel launch");
+  BHIP(launch_steps_batch(discrete, b->occ, a, st, cooperative), "batched step kernel launch");
   if (timed) BHIP(hipEventRecord(b->ev1, st), "event record");
   BHIP(launch_fill_u32(reinterpret_cast<unsigned*>(w + b->off_eacc), (size_t)b->count * b->rp, 0u, st),
        "clear energies");
@@ -446,7 +456,8 @@ gsb_status gsb_batch_create(int32_t count, const int32_t* n, int32_t replicas, g
     b->have_j.assign(count, 0);
     b->have_eig.assign(count, 0);
     b->tile_fixed.assign(count, 0);
-    for (auto& u : b->us) u.assign(count, 0.0);
+    for (auto& per_occ : b->us)
+      for (auto& u : per_occ) u.assign(count, 0.0);
     for (auto* v : {&b->off_j, &b->off_x, &b->off_y, &b->off_p, &b->off_q, &b->off_s8, &b->off_sync})
       v->assign(count, 0);
   } catch (...) {
@@ -548,6 +559,20 @@ gsb_status gsb_batch_set_coupling(gsb_batch* b, int32_t k, const float* J, doubl
 gsb_status gsb_batch_set(gsb_batch* b, int32_t k, int32_t option, double v) {
   set_last_error("");
   if (!b) return bfail(GSB_EINVAL, "batch is NULL");
+  if (option == GSB_BATCH_OCCUPANCY) {
+    if (k != -1) return bfail(GSB_EINVAL, "batch-wide option: pass k = -1");
+    const int iv = (int)v;
+    if ((double)iv != v || iv < 0 || iv > 2) return bfail(GSB_EINVAL, "GSB_BATCH_OCCUPANCY is 0, 1 or 2");
+    if (iv) {
+      gsb_status s = device_facts(b);
+      if (s != GSB_OK) return s;
+      if (b->grid[iv - 1] == 0) return bfail(GSB_EUNSUPPORTED, "this device does not run the kernel at that occupancy");
+      b->occ = iv;
+    }
+    b->occ_fixed = iv;
+    drop_graph(b);
+    return GSB_OK;
+  }
   if (option == GSB_BATCH_GRAPH || option == GSB_BATCH_INIT_MODE) {
     if (k != -1) return bfail(GSB_EINVAL, "batch-wide option: pass k = -1");
     const int iv = (int)v;
@@ -593,9 +618,10 @@ gsb_status gsb_batch_get(gsb_batch* b, int32_t k, int32_t option, double* v) {
   if (option == GSB_BATCH_GRID) {
     gsb_status s = device_facts(b);
     if (s != GSB_OK) return s;
-    *v = b->grid;
+    *v = b->grid[b->occ - 1];
     return GSB_OK;
   }
+  if (option == GSB_BATCH_OCCUPANCY) { *v = b->occ; return GSB_OK; }
   if (k < 0 || k >= b->count) return bfail(GSB_EINVAL, "instance index out of range");
   switch (option) {
     case GSB_BATCH_N: *v = b->n[k]; return GSB_OK;
@@ -612,14 +638,14 @@ gsb_status gsb_batch_get(gsb_batch* b, int32_t k, int32_t option, double* v) {
     case GSB_BATCH_TILE_ROWS: {
       gsb_status s = device_facts(b);
       if (s != GSB_OK) return s;
-      *v = choose_tile(b, k);
+      *v = choose_tile(b, k, b->occ);
       return GSB_OK;
     }
     case GSB_BATCH_STEP_US: {
       gsb_status s = device_facts(b);
       if (s != GSB_OK) return s;
-      const int t = tile_index(choose_tile(b, k));
-      *v = t >= 0 ? b->us[t][k] : 0.0;
+      const int t = tile_index(choose_tile(b, k, b->occ));
+      *v = t >= 0 ? b->us[b->occ - 1][t][k] : 0.0;
       return GSB_OK;
     }
     default:
@@ -634,46 +660,68 @@ gsb_status gsb_batch_autotune(gsb_batch* b, int32_t variant, double A, int32_t t
   s = device_facts(b);
   if (s != GSB_OK) return s;
   const bool discrete = variant == GSB_DSB || variant == GSB_GDSB;
+  if (!b->ev0) {
+    BHIP(hipEventCreate(&b->ev0), "event create");
+    BHIP(hipEventCreate(&b->ev1), "event create");
+  }
   std::vector<int> tiles(b->count);
-  for (int t = 0; t < 3; ++t) {
-    bool any = false;
-    for (int k = 0; k < b->count; ++k) {
-      int bm = b->tile_fixed[k] ? b->tile_fixed[k] : kTiles[t];
-      if (b->np[k] / bm > b->cap || b->np[k] < bm) bm = choose_tile(b, k);  // keep the queue runnable
-      tiles[k] = bm;
-      any = any || bm == kTiles[t];
+  double best_ms = -1.0;
+  int best_occ = b->occ;
+  for (int occ = 1; occ <= 2; ++occ) {
+    if ((b->occ_fixed && occ != b->occ_fixed) || b->grid[occ - 1] == 0) continue;
+    b->occ = occ;
+    const int cap = b->cap[occ - 1];
+    for (int t = 0; t < 3; ++t) {
+      bool any = false;
+      for (int k = 0; k < b->count; ++k) {
+        int bm = b->tile_fixed[k] ? b->tile_fixed[k] : kTiles[t];
+        if (b->np[k] / bm > cap || b->np[k] < bm) bm = choose_tile(b, k, occ);  // keep the queue runnable
+        tiles[k] = bm;
+        any = any || bm == kTiles[t];
+      }
+      if (!any) continue;
+      s = prepare(b, variant, A, trial_steps, seed, tiles.data(), true);
+      if (s != GSB_OK) return s;
+      s = enqueue_run(b, discrete, true, false, b->stream);
+      if (s != GSB_OK) return s;
+      s = check_status(b);
+      if (s != GSB_OK) return s;
+      const size_t nslots = (size_t)b->h_qoff[kBatchXcds + 1];
+      std::vector<unsigned long long> clk(2 * nslots);
+      BHIP(hipMemcpy(clk.data(), b->d_clk, clk.size() * 8, hipMemcpyDeviceToHost), "read clocks");
+      // a gang runs from its last member's start to its last member's end; every slot
+      // of the queue that served it was taken exactly once
+      std::vector<double> worst(b->count, 0.0);
+      for (size_t i = 0; i < nslots;) {
+        const BatchSlot& sl = b->h_slots[i];
+        const int k = sl.inst, w = b->h_inst[k].nb;
+        unsigned long long s0 = 0, e0 = 0;
+        bool served = true;
+        for (int j = 0; j < w; ++j) {
+          const unsigned long long a0 = clk[2 * (i + j)], a1 = clk[2 * (i + j) + 1];
+          if (a1 == 0) served = false;
+          s0 = std::max(s0, a0);
+          e0 = std::max(e0, a1);
+        }
+        if (served && e0 > s0) worst[k] = std::max(worst[k], (double)(e0 - s0) / b->wall_hz * 1e6 / trial_steps);
+        i += w;
+      }
+      for (int k = 0; k < b->count; ++k)
+        if (tiles[k] == kTiles[t] && worst[k] > 0) b->us[occ - 1][t][k] = worst[k];
     }
-    if (!any) continue;
-    s = prepare(b, variant, A, trial_steps, seed, tiles.data(), true);
+    // the whole batch with this occupancy's fastest tiles, timed
+    s = prepare(b, variant, A, trial_steps, seed, nullptr, false);
     if (s != GSB_OK) return s;
-    s = enqueue_run(b, discrete, true, false, b->stream);
+    s = enqueue_run(b, discrete, true, true, b->stream);
     if (s != GSB_OK) return s;
     s = check_status(b);
     if (s != GSB_OK) return s;
-    const size_t nslots = (size_t)b->h_qoff[kBatchXcds + 1];
-    std::vector<unsigned long long> clk(2 * nslots);
-    BHIP(hipMemcpy(clk.data(), b->d_clk, clk.size() * 8, hipMemcpyDeviceToHost), "read clocks");
-    // a gang runs from its last member's start to its last member's end; every slot of
-    // the queue that served it was taken exactly once
-    std::vector<double> worst(b->count, 0.0);
-    std::vector<unsigned long long> st, en;
-    for (size_t i = 0; i < nslots;) {
-      const BatchSlot& sl = b->h_slots[i];
-      const int k = sl.inst, w = b->h_inst[k].nb;
-      unsigned long long s0 = 0, e0 = 0;
-      bool served = true;
-      for (int j = 0; j < w; ++j) {
-        const unsigned long long a0 = clk[2 * (i + j)], a1 = clk[2 * (i + j) + 1];
-        if (a1 == 0) served = false;
-        s0 = std::max(s0, a0);
-        e0 = std::max(e0, a1);
-      }
-      if (served && e0 > s0) worst[k] = std::max(worst[k], (double)(e0 - s0) / b->wall_hz * 1e6 / trial_steps);
-      i += w;
-    }
-    for (int k = 0; k < b->count; ++k)
-      if (tiles[k] == kTiles[t] && worst[k] > 0) b->us[t][k] = worst[k];
+    float ms = 0;
+    BHIP(hipEventElapsedTime(&ms, b->ev0, b->ev1), "event elapsed time");
+    if (best_ms < 0 || ms < best_ms) { best_ms = ms; best_occ = occ; }
   }
+  b->occ = best_occ;
+  b->timed = false;
   b->ran = false;
   drop_graph(b);
   return GSB_OK;

@@ -140,8 +140,9 @@ hipError_t launch_spins(const float* x, int n_out, int np, int r_first, int r_co
 // Batched instances (FP8 product, variants by `discrete`): the persistent queue kernel,
 // its co-resident workgroups per CU, and the per-instance start, energy and best kernels
 // over `count` instances (np_max: the largest np; rp replicas each, r_count of them real).
-hipError_t launch_steps_batch(bool discrete, const BatchArgs& b, hipStream_t stream, bool cooperative);
-int batch_workgroups_per_cu(bool discrete, int lds_bytes);
+// occ: workgroups per CU the kernel variant is built for (1 or 2).
+hipError_t launch_steps_batch(bool discrete, int occ, const BatchArgs& b, hipStream_t stream, bool cooperative);
+int batch_workgroups_per_cu(bool discrete, int occ, int lds_bytes);
 hipError_t launch_init_batch(const StepArgs* inst, const BatchInst* bi, int count, int np_max, int rp, int mode,
                              hipStream_t stream);
 hipError_t launch_energy_batch(const StepArgs* inst, const BatchInst* bi, int count, int np_max, int rp,

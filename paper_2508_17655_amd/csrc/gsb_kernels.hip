@@ -73,7 +73,7 @@ __device__ __forceinline__ void gemm_tile_fp32(const uint8_t* jrows, __amdgpu_bu
 // eqs. (7), (3), (4), (5) (see the update below); the control strength may differ per
 // replica (a.acol).
 // ---------------------------------------------------------------------------------------
-template <int FORM, bool DISC, bool TANG, int BM, bool LJ = false>
+template <int FORM, bool DISC, bool TANG, int BM, bool LJ = false, int QD = kKStepsUnroll>
 __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int& s_flag, int& s_local,
                                            uint8_t* lds_j = nullptr, int lds_bytes = 0) {
   static_assert(!LJ || FORM == kFormFP8, "J rows in LDS: FP8 product (FP4 J) only");
@@ -191,7 +191,8 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
       // never written by an LDS read while a global load to them may be in flight (which
       // would force a full wait).  Segment lengths are multiples of kPF; the last kPF
       // k-steps of each are peeled without Q loads.
-      constexpr int kPF = kKStepsUnroll;
+      constexpr int kPF = QD;
+      static_assert(kKStepsUnroll % kPF == 0, "segments are multiples of kKStepsUnroll");
       v8i bq[kPF][2];
       auto load_b = [&](int ks, v8i* dst) {
 #pragma unroll
@@ -539,8 +540,11 @@ __device__ __forceinline__ StepArgs uniform_args(const StepArgs& a) {
   return u;
 }
 
-template <bool DISC>
-__global__ void __launch_bounds__(kThreads, 1) k_steps_batch(BatchArgs b) {
+// OCC workgroups per CU: with 2, one workgroup's update and barrier overlap the other's
+// K loop; registers then allow a Q prefetch depth of 2 and LDS half as many J rows.
+template <bool DISC, int OCC>
+__global__ void __launch_bounds__(kThreads, OCC) k_steps_batch(BatchArgs b) {
+  constexpr int QD = OCC == 1 ? kKStepsUnroll : kKStepsUnroll / 2;
   __shared__ int s_flag;
   __shared__ int s_local;
   __shared__ int s_slot;
@@ -588,9 +592,12 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps_batch(BatchArgs b) {
     const BatchSlot t{ufirst(tv.inst), ufirst(tv.g), ufirst(tv.mb), ufirst(tv.bm)};
     const StepArgs a = uniform_args(b.inst[t.inst]);
     if (b.clk && tid == 0) b.clk[2 * slot] = wall_clock64();
-    if (t.bm == 64) steps_tile<kFormFP8, DISC, false, 64, true>(a, t.g, t.mb, s_flag, s_local, lds_dyn, b.lds_bytes);
-    else if (t.bm == 128) steps_tile<kFormFP8, DISC, false, 128, true>(a, t.g, t.mb, s_flag, s_local, lds_dyn, b.lds_bytes);
-    else steps_tile<kFormFP8, DISC, false, 256, true>(a, t.g, t.mb, s_flag, s_local, lds_dyn, b.lds_bytes);
+    if (t.bm == 64)
+      steps_tile<kFormFP8, DISC, false, 64, true, QD>(a, t.g, t.mb, s_flag, s_local, lds_dyn, b.lds_bytes);
+    else if (t.bm == 128)
+      steps_tile<kFormFP8, DISC, false, 128, true, QD>(a, t.g, t.mb, s_flag, s_local, lds_dyn, b.lds_bytes);
+    else
+      steps_tile<kFormFP8, DISC, false, 256, true, QD>(a, t.g, t.mb, s_flag, s_local, lds_dyn, b.lds_bytes);
     __syncthreads();  // the next tile overwrites the LDS copy of J
     if (b.clk && tid == 0) b.clk[2 * slot + 1] = wall_clock64();
   }
@@ -1341,9 +1348,16 @@ hipError_t launch_best(const double* energies, int r_count, int* best_idx, doubl
   return hipGetLastError();
 }
 
-hipError_t launch_steps_batch(bool discrete, const BatchArgs& b, hipStream_t stream, bool cooperative) {
-  const void* k = discrete ? reinterpret_cast<const void*>(&k_steps_batch<true>)
-                           : reinterpret_cast<const void*>(&k_steps_batch<false>);
+const void* batch_kernel(bool discrete, int occ) {
+  if (occ == 2)
+    return discrete ? reinterpret_cast<const void*>(&k_steps_batch<true, 2>)
+                    : reinterpret_cast<const void*>(&k_steps_batch<false, 2>);
+  return discrete ? reinterpret_cast<const void*>(&k_steps_batch<true, 1>)
+                  : reinterpret_cast<const void*>(&k_steps_batch<false, 1>);
+}
+
+hipError_t launch_steps_batch(bool discrete, int occ, const BatchArgs& b, hipStream_t stream, bool cooperative) {
+  const void* k = batch_kernel(discrete, occ);
   if (b.lds_bytes > 0) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, b.lds_bytes);
     if (e != hipSuccess) return e;
@@ -1354,9 +1368,8 @@ hipError_t launch_steps_batch(bool discrete, const BatchArgs& b, hipStream_t str
   return hipLaunchKernel(k, dim3(b.grid), dim3(kThreads), args, (size_t)b.lds_bytes, stream);
 }
 
-int batch_workgroups_per_cu(bool discrete, int lds_bytes) {
-  const void* k = discrete ? reinterpret_cast<const void*>(&k_steps_batch<true>)
-                           : reinterpret_cast<const void*>(&k_steps_batch<false>);
+int batch_workgroups_per_cu(bool discrete, int occ, int lds_bytes) {
+  const void* k = batch_kernel(discrete, occ);
   if (lds_bytes > 0 && hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes) != hipSuccess)
     return 0;
   int per_cu = 0;

@@ -27,7 +27,8 @@ GSB_INIT_X, GSB_INIT_XY, GSB_INIT_PM01, GSB_INIT_PAIRS = 0, 1, 2, 3
  GSB_OPT_STEP, GSB_OPT_REPLICAS, GSB_OPT_DT_STABLE, GSB_OPT_N_DYN) = range(10)
 
 (GSB_BATCH_C, GSB_BATCH_DT, GSB_BATCH_LAMBDA_MAX, GSB_BATCH_LAMBDA_MIN, GSB_BATCH_TILE_ROWS, GSB_BATCH_STEP_US,
- GSB_BATCH_N, GSB_BATCH_GRAPH, GSB_BATCH_INIT_MODE, GSB_BATCH_COUNT, GSB_BATCH_REPLICAS, GSB_BATCH_GRID) = range(12)
+ GSB_BATCH_N, GSB_BATCH_GRAPH, GSB_BATCH_INIT_MODE, GSB_BATCH_COUNT, GSB_BATCH_REPLICAS, GSB_BATCH_GRID,
+ GSB_BATCH_OCCUPANCY) = range(13)
 
 VARIANTS = {"bsb": GSB_BSB, "dsb": GSB_DSB, "gbsb": GSB_GBSB, "gsb": GSB_GBSB, "gdsb": GSB_GDSB}
 PRECISIONS = {"fp32": GSB_PREC_FP32, "bf16x2": GSB_PREC_BF16X2, "fp8": GSB_PREC_FP8, "fix16": GSB_PREC_FIX16}

@@ -121,6 +121,28 @@ def test_every_tile_shape_gives_the_same_bits():
     b.close()
 
 
+def test_two_workgroups_per_cu_give_the_same_bits():
+    gsb = _gsb()
+    M, A, seed = 40, 0.2, 13
+    say("case batch occupancy 1 vs 2")
+    insts = _instances(SIZES)
+    b = _batch(insts)
+    b.set(-1, gsb.GSB_BATCH_OCCUPANCY, 1)
+    b.run("gbsb", A=A, steps=M, seed=seed)
+    ref = [b.state(k) for k in range(len(SIZES))]
+    b.set(-1, gsb.GSB_BATCH_OCCUPANCY, 2)
+    assert b.get(-1, gsb.GSB_BATCH_GRID) == 2 * b.get(-1, gsb.GSB_BATCH_GRID) // 2
+    for rows in (64, 128, 256):  # the wider XCD queues also admit 64-row tiles of larger instances
+        for k in range(len(SIZES)):
+            b.set(k, gsb.GSB_BATCH_TILE_ROWS, rows)
+        b.run("gbsb", A=A, steps=M, seed=seed)
+        for k in range(len(SIZES)):
+            for a_, c_, what in zip(b.state(k), ref[k], "xyp"):
+                _check_exact(a_, c_, f"occupancy 2 tile {rows} instance {k} {what}")
+    _compare_with_oracle(b, insts, "gbsb", A, M, seed)
+    b.close()
+
+
 def test_batch_equals_single_instance_path():
     gsb = _gsb()
     M, A, seed = 50, 0.3, 21
