@@ -45,7 +45,7 @@ def _finite(v: float):
 
 
 # sources that determine the register-resident step kernel's machine code
-RJ_SOURCES = ("gsb_steps_rj.hip", "gsb_device.h", "gsb_internal.h")
+RJ_SOURCES = ("gsb_steps_rj.hip", "gsb_device.h", "gsb_types.h")
 
 
 def kernel_source_hash() -> str:

@@ -2,7 +2,7 @@
 // types, buffer resources, the replica-group barrier and the fragment-major operand
 // encodings.  Included by the kernel translation units only.
 #pragma once
-#include "gsb_internal.h"
+#include "gsb_types.h"
 
 #pragma clang fp contract(off)
 

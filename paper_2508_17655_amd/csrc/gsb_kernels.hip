@@ -13,6 +13,7 @@
 // binary32 operation per arithmetic operator, in the order written, so the sign and E4M3
 // forms reproduce a strict binary32 evaluation bit for bit.
 #include "gsb_device.h"
+#include "gsb_internal.h"
 
 #include <algorithm>
 #include <type_traits>
