@@ -274,3 +274,33 @@ def test_full_workload_sampled():
         _check_exact(p[rows], po, f"instance {k} p")
         assert np.all(np.abs(x) <= 1.0)
     b.close()
+
+
+def test_many_ragged_replicas():
+    """1000 replicas per instance (padded to 1024: 8 to 32 replica groups per instance,
+    depending on the tile), sign and E4M3 products, sampled replicas against the oracle."""
+    gsb = _gsb()
+    M, A, seed, reps = 30, 0.3, 17, 1000
+    say("case batch R=1000 sizes=[150, 1100]")
+    insts = [(instances.dense_pm1(150, 21), instances.paper_c(150), 1.25),
+             (instances.erdos_renyi_pm1(1100, 0.03, 22), 0.0, 0.0)]
+    b = _batch(insts, replicas=reps)
+    for variant, form in (("gdsb", oracle.FORM_EXACT), ("gbsb", oracle.FORM_E4M3)):
+        b.run(variant, A=A, steps=M, seed=seed)
+        for k, (J, _, _) in enumerate(insts):
+            n = J.shape[0]
+            c, dt = b.params(k)
+            rows = np.array([0, 511, 512, 999])
+            x0, y0 = oracle.init_state(n, reps, seed + k)
+            xo, yo, po = oracle.run(J.astype(np.float64), oracle.VARIANTS[variant], A=A, dt=dt, c=c, steps=M,
+                                    x=x0[rows], y=y0[rows], form=form, mode="fp32")
+            x, y, p = b.state(k)
+            assert x.shape == (reps, n)
+            _check_exact(x[rows], xo, f"{variant} instance {k} x")
+            _check_exact(y[rows], yo, f"{variant} instance {k} y")
+            E = b.energy(k)
+            assert E.shape == (reps,)
+            _check_exact(E[rows], oracle.energy(J.astype(np.float64), oracle.spins(xo)), f"{variant} instance {k} E")
+        e, r = b.best()
+        assert np.all((r >= 0) & (r < reps))
+    b.close()
