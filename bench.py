@@ -446,6 +446,11 @@ def main():
         out["dt_study"] = dt_study(J, c)
     if not args.no_precision:
         out["precision"] = precision_forms(J, c)
+    # this device's measured ceilings (MFMA rates, streaming bandwidths, clock), beside the
+    # published peaks the roofline fractions use
+    ceil = gsb.gsb_device_ceilings()
+    ceil["headline_frac_of_measured_fp4xfp8"] = achieved * 1e12 / ceil["mfma_fp4xfp8_flops"]
+    out["ceilings"] = ceil
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(J.astype(np.float64), c)
     print(json.dumps(out))

@@ -347,6 +347,13 @@ gsb_status compute_energy(gsb_ctx* c) {
 extern "C" {
 
 const char* gsb_last_error(void) { return g_err.c_str(); }
+
+gsb_status gsb_device_ceilings(double* out, int32_t count) {
+  g_err.clear();
+  if (!out || count < 1) return fail(GSB_EINVAL, "out must hold at least one value");
+  HIP_TRY(measure_ceilings(out, count), "ceiling probes");
+  return GSB_OK;
+}
 const char* gsb_version(void) { return "gsb-mi355x 0.1 (gfx950)"; }
 
 gsb_status gsb_create(const float* J, const float* h, int32_t n, gsb_ctx** out) {
