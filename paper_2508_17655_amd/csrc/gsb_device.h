@@ -84,10 +84,14 @@ __device__ __forceinline__ bool group_sync(unsigned* ctr, unsigned target, int l
 //   BF16  : 4096 B per plane = [sub 4][lane 64][8 bf16]; kk = 32*sub + 8*(lane/16) + e
 //   FP32  : 8192 B = [grp 8][lane 64][4 f32];  kk = 16*grp + 4*(lane/16) + t, where
 //           element t feeds the t-th of four 16x16x4 MFMAs of that group.
-//   FIX16 : 2048 B per plane = [half 2][lane 64][16 x int8]; kk = 64*half + 16*(lane/16) + b
-//           (16x16x64 int8 MFMA); plane 0 holds hi, plane 1 lo of q = rint(x 2^14) =
-//           256 hi + lo, hi in [-64, 64], lo in [-128, 127].
+//   FIX16 : 32x32x32 int8 MFMA.  Per (32-replica block, k-step): 4 KiB per plane =
+//           [quarter 4][lane 64][16 x int8]; lane = r%32 + 32*((kk%32)/16),
+//           kk = 32*quarter + 16*(lane/32) + b; plane 0 holds hi, plane 1 lo of
+//           q = rint(x 2^14) = 256 hi + lo, hi in [-64, 64], lo in [-128, 127].  J: the same
+//           per (32-row tile, k-step), rows in place of replicas.
 // (kk = k mod 128.)  J uses the same layouts with the row i in place of the replica r.
+// store_operand receives the 16x16 tile origin (ibase, rcol) of the lane's elements, or
+// for FIX16 the lane's own first element (row ibase, ibase % 4 == 0, column rcol).
 // ---------------------------------------------------------------------------------------
 template <int FORM, bool DISC>
 __device__ __forceinline__ void store_operand(uint8_t* qbuf, size_t plane_bytes, int nks,
@@ -139,8 +143,11 @@ __device__ __forceinline__ void store_operand(uint8_t* qbuf, size_t plane_bytes,
       wh |= (unsigned)(hi & 0xFF) << (8 * v);
       wl |= (unsigned)(lo & 0xFF) << (8 * v);
     }
-    const int lanep = (lane & 15) + 16 * ((kk0 & 63) >> 4);
-    const size_t off = ((size_t)(rb * nks + kc) * 2 + (kk0 >> 6)) * 1024 + lanep * 16 + (kk0 & 15);
+    (void)kk0;
+    (void)rb;
+    const int lanep = (rcol & 31) + 32 * ((ibase & 31) >> 4);
+    const size_t off =
+        ((size_t)((rcol >> 5) * nks + kc) * 4 + ((ibase & 127) >> 5)) * 1024 + lanep * 16 + (ibase & 15);
     *reinterpret_cast<unsigned*>(qbuf + off) = wh;
     *reinterpret_cast<unsigned*>(qbuf + plane_bytes + off) = wl;
   } else {

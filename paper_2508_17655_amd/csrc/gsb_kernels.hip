@@ -77,7 +77,7 @@ __device__ __forceinline__ void gemm_tile_fp32(const uint8_t* jrows, __amdgpu_bu
 template <int FORM, bool DISC, bool TANG, int BM, bool LJ = false, int QD = kKStepsUnroll>
 __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int& s_flag, int& s_local,
                                            uint8_t* lds_j = nullptr, int lds_bytes = 0) {
-  static_assert(!LJ || FORM == kFormFP8, "J rows in LDS: FP8 product (FP4 J) only");
+  static_assert(!LJ || FORM == kFormFP8 || FORM == kFormFIX16, "J rows in LDS: FP8 (FP4 J) or FIX16 (int8 J)");
   static_assert(!TANG || (FORM == kFormFP32 && !DISC), "the tangent needs the continuous binary32 product");
   static_assert(BM == 64 || BM == 128 || BM == 256, "tile rows");
   constexpr int BN = 8192 / BM;
@@ -99,17 +99,34 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
   const size_t jblk = FORM == kFormFP8 ? 1024 : operand_block_bytes(FORM);  // FP8 product: FP4 J
   const size_t plane_bytes = a.q_buf_bytes / operand_planes(FORM);
 
-  // J rows of this wave: 4 row tiles x nks k-steps, contiguous in the layout.
+  // J rows of this wave: 4 row tiles x nks k-steps, contiguous in the layout (FIX16: 2
+  // row tiles of 32, the same bytes).
   const uint8_t* jrows = static_cast<const uint8_t*>(a.jf) + (size_t)(mb * BM / 16 + 4 * wrow) * nks * jblk;
 
-  // State of this wave's 64 x 32 tile: lane holds rows 4*(lane/16)+v of column lane%16.
+  // Elements of the wave's 64 x 32 tile held by this lane: rows row0 + er(rt, ct) + v
+  // (v < 4) of column col0 + ec(ct).  With 16x16 MFMA tiles (4 x 2 of them) that is rows
+  // 16 rt + 4 (lane/16) + v of column 16 ct + lane%16; FIX16 uses 32x32 int8 tiles (2 x 1),
+  // whose lane holds rows 32 (g/4) + 8 (g%4) + 4 (lane/32) + v of column lane%32 for
+  // register group g = 2 rt + ct.
+  constexpr bool T32 = FORM == kFormFIX16;
+  auto er = [&](int rt, int ct) {
+    return T32 ? 32 * (rt >> 1) + 8 * ((2 * rt + ct) & 3) + 4 * (lane >> 5) : rt * 16 + 4 * (lane >> 4);
+  };
+  auto ec = [&](int ct) { return T32 ? (lane & 31) : ct * 16 + (lane & 15); };
+  // operand of the lane's elements (store_operand takes the 16x16 tile origin, or for
+  // FIX16 the lane's own first element)
+  auto store_q = [&](uint8_t* buf, int rt, int ct, const float* xv) {
+    store_operand<FORM, DISC>(buf, plane_bytes, nks, row0 + (T32 ? er(rt, ct) : rt * 16),
+                              col0 + (T32 ? ec(ct) : ct * 16), lane, xv);
+  };
+
   float xs[4][2][4], ys[4][2][4], ps[4][2][4];
 #pragma unroll
   for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) {
-      const int i = row0 + rt * 16 + 4 * (lane >> 4);
-      const int r = col0 + ct * 16 + (lane & 15);
+      const int i = row0 + er(rt, ct);
+      const int r = col0 + ec(ct);
       const size_t o = (size_t)r * a.np + i;
       v4f vx = *reinterpret_cast<const v4f*>(a.x + o);
       v4f vy = *reinterpret_cast<const v4f*>(a.y + o);
@@ -120,7 +137,18 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
 
   // Leading k-steps of this workgroup's J rows into LDS: [row tile][k-step][lane][16 B].
   int nks_l = 0;
-  if constexpr (LJ) {
+  if constexpr (LJ && FORM == kFormFIX16) {
+    // int8 J: the workgroup's BM rows are one contiguous BM * np byte range; all of it or
+    // none (the launch gives BM * np bytes of LDS when it fits)
+    const size_t bytes = (size_t)BM * a.np;
+    nks_l = bytes <= (size_t)lds_bytes ? nks : 0;
+    if (nks_l) {
+      const uint8_t* jwg = static_cast<const uint8_t*>(a.jf) + (size_t)mb * BM * a.np;
+      for (size_t c = tid; c < bytes / 16; c += kThreads)
+        *reinterpret_cast<v4i*>(lds_j + c * 16) = *reinterpret_cast<const v4i*>(jwg + c * 16);
+    }
+    __syncthreads();
+  } else if constexpr (LJ) {
     {
       constexpr int kTilesWG = BM / 16;
       nks_l = min(nks, lds_bytes / (kTilesWG * 1024)) / kKStepsUnroll * kKStepsUnroll;
@@ -136,7 +164,9 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
     }
   }
   // this wave's row tiles in LDS
-  const uint8_t* jlds = LJ ? lds_j + (size_t)(4 * wrow) * nks_l * 1024 + lane * 16 : nullptr;
+  const uint8_t* jlds = !LJ ? nullptr
+                        : FORM == kFormFIX16 ? lds_j + (size_t)(2 * wrow) * nks * 4096 + lane * 16
+                                             : lds_j + (size_t)(4 * wrow) * nks_l * 1024 + lane * 16;
 
   // Handshake: learn whether all members of this group run on one XCD.
   if (tid == 0) {
@@ -165,7 +195,7 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
     for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct)
-        store_operand<FORM, DISC>(a.q, plane_bytes, nks, row0 + rt * 16, col0 + ct * 16, lane, xs[rt][ct]);
+        store_q(a.q, rt, ct, xs[rt][ct]);
     alive = group_sync(ctr, (unsigned)a.nb, local, abort_flag, a.status, &s_flag);
   }
 
@@ -313,76 +343,91 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
         __builtin_amdgcn_sched_barrier(0);
       }
     } else if constexpr (FORM == kFormFIX16) {
-      // two int8 passes (hi, lo planes; the sign operand has lo = 0), exact int32 sums;
+      // two int8 passes (hi, lo planes; the sign operand has lo = 0) on 32x32x32 MFMAs
+      // (the 16x16x64 shape runs at ~58% of their rate here), exact int32 sums;
       // G = 256 G_hi + G_lo is exact in int32 and rounded to binary32 once, then scaled.
-      // Software pipeline over half k-steps (64 spins): Q fragments of both planes are
-      // fetched kPFs half-steps ahead and J fragments one ahead.  2 nks is a multiple of
-      // kPFs; the last kPFs half-steps are peeled without loads.
+      // Software pipeline over quarter k-steps (32 spins, 4 MFMAs each): Q fragments of
+      // both planes are fetched kQS quarters ahead and J fragments kJS ahead, in register
+      // rings whose indices are compile-time constants.  4 nks is a multiple of kQS; the
+      // last kQS quarters are peeled without Q loads.
       constexpr int planes = DISC ? 1 : 2;
-      constexpr int kPFs = kKStepsUnroll;
-      v4i iacc[2][4][2];
+      constexpr int kQS = 2 * kKStepsUnroll;  // 8 quarters
+      constexpr int kJS = 3, kJR = 4;         // J distance and ring (kJR divides kQS)
+      typedef int v16i __attribute__((ext_vector_type(16)));
+      v16i iacc[2][2];  // [plane][32-row tile]
 #pragma unroll
       for (int pl = 0; pl < 2; ++pl)
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
+        for (int t = 0; t < 2; ++t) iacc[pl][t] = v16i{};
+      const int nsub = 4 * nks;  // a multiple of 16
+      const int cb = col0 >> 5;  // the wave's 32-column block
+      v4i aj[kJR][2];
+      v4i bq[kQS][planes];
+      auto load_a_glb = [&](int sb, v4i* dst) {
 #pragma unroll
-          for (int ct = 0; ct < 2; ++ct) iacc[pl][rt][ct] = v4i{0, 0, 0, 0};
-      const int nsub = 2 * nks;
-      v4i aj[2][4];
-      v4i bq[kPFs][planes][2];
-      auto load_a = [&](int sb, v4i* dst) {
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
-          dst[rt] = *reinterpret_cast<const v4i*>(jrows + ((size_t)(rt * nks + (sb >> 1)) * 2 + (sb & 1)) * 1024 +
-                                                  lane * 16);
+        for (int t = 0; t < 2; ++t)
+          dst[t] = *reinterpret_cast<const v4i*>(jrows + ((size_t)(t * nks + (sb >> 2)) * 4 + (sb & 3)) * 1024 +
+                                                 lane * 16);
       };
-      auto load_b = [&](int sb, v4i (*dst)[2]) {
+      auto load_a_lds = [&](int sb, v4i* dst) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+          dst[t] = *reinterpret_cast<const v4i*>(jlds + ((size_t)(t * nks + (sb >> 2)) * 4 + (sb & 3)) * 1024);
+      };
+      auto load_b = [&](int sb, v4i* dst) {
+#pragma unroll
+        for (int pl = 0; pl < planes; ++pl) {
+          const unsigned base =
+              (unsigned)(pl * plane_bytes + ((size_t)(cb * nks + (sb >> 2)) * 4 + (sb & 3)) * 1024 + lane * 16);
+          dst[pl] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kQPolicy));
+        }
+      };
+      auto mfmas = [&](const v4i* aa, const v4i* bb) {
 #pragma unroll
         for (int pl = 0; pl < planes; ++pl)
 #pragma unroll
-          for (int ct = 0; ct < 2; ++ct) {
-            const unsigned base = (unsigned)(pl * plane_bytes + ((size_t)((rb0 + ct) * nks + (sb >> 1)) * 2 + (sb & 1)) *
-                                                                    1024 + lane * 16);
-            dst[pl][ct] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kQPolicy));
+          for (int t = 0; t < 2; ++t)
+            iacc[pl][t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(aa[t], bb[pl], iacc[pl][t], 0, 0, 0);
+      };
+      // one pipeline per J source (LDS or L2), so no register is written by both kinds
+      // of load
+      auto pipeline = [&](auto load_a) {
+#pragma unroll
+        for (int u = 0; u < kQS; ++u) load_b(u, bq[u]);
+#pragma unroll
+        for (int d = 0; d < kJS; ++d) load_a(d, aj[d]);
+        int s0 = 0;
+        for (; s0 < nsub - kQS; s0 += kQS) {
+#pragma unroll
+          for (int u = 0; u < kQS; ++u) {
+            load_a(s0 + u + kJS, aj[(u + kJS) % kJR]);  // < nsub: s0 <= nsub - 2 kQS
+            __builtin_amdgcn_sched_barrier(0);
+            mfmas(aj[u % kJR], bq[u]);
+            load_b(s0 + u + kQS, bq[u]);
+            __builtin_amdgcn_sched_barrier(0);
           }
-      };
-      auto mfmas = [&](const v4i* aa, v4i (*bb)[2]) {
+        }
 #pragma unroll
-        for (int pl = 0; pl < planes; ++pl)
-#pragma unroll
-          for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-            for (int ct = 0; ct < 2; ++ct)
-              iacc[pl][rt][ct] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aa[rt], bb[pl][ct], iacc[pl][rt][ct], 0, 0, 0);
-      };
-#pragma unroll
-      for (int u = 0; u < kPFs; ++u) load_b(u, bq[u]);
-      load_a(0, aj[0]);
-      int s0 = 0;
-      for (; s0 < nsub - kPFs; s0 += kPFs) {
-#pragma unroll
-        for (int u = 0; u < kPFs; ++u) {
-          load_a(s0 + u + 1, aj[(u + 1) & 1]);
+        for (int u = 0; u < kQS; ++u) {
+          if (u + kJS < kQS) load_a(s0 + u + kJS, aj[(u + kJS) % kJR]);
           __builtin_amdgcn_sched_barrier(0);
-          mfmas(aj[u & 1], bq[u]);
-          load_b(s0 + u + kPFs, bq[u]);
+          mfmas(aj[u % kJR], bq[u]);
           __builtin_amdgcn_sched_barrier(0);
         }
-      }
-#pragma unroll
-      for (int u = 0; u < kPFs; ++u) {
-        if (u + 1 < kPFs) load_a(s0 + u + 1, aj[(u + 1) & 1]);
-        __builtin_amdgcn_sched_barrier(0);
-        mfmas(aj[u & 1], bq[u]);
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      };
+      if (LJ && nks_l == nks)
+        pipeline(load_a_lds);
+      else
+        pipeline(load_a_glb);
 #pragma unroll
       for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            acc[rt][ct][v] = (float)(iacc[0][rt][ct][v] * 256 + iacc[1][rt][ct][v]) * 0x1p-14f;
+          for (int v = 0; v < 4; ++v) {
+            const int j = 4 * ((2 * rt + ct) & 3) + v;
+            acc[rt][ct][v] = (float)(iacc[0][rt >> 1][j] * 256 + iacc[1][rt >> 1][j]) * 0x1p-14f;
+          }
     } else {  // FP32
       gemm_tile_fp32(jrows, qr, rb0, nks, lane, acc);
     }
@@ -431,7 +476,7 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
         }
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
-          store_operand<FORM, DISC>(qnext, plane_bytes, nks, row0 + rt * 16, col0 + ct * 16, lane, xs[rt][ct]);
+          store_q(qnext, rt, ct, xs[rt][ct]);
       }
     } else {
     if (a.tape) {  // record this step's input state (reverse pass)
@@ -473,7 +518,7 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
           ys[rt][ct][v] = hit ? 0.0f : yn;
           ps[rt][ct][v] = pn;
         }
-        store_operand<FORM, DISC>(qnext, plane_bytes, nks, row0 + rt * 16, col0 + ct * 16, lane, xs[rt][ct]);
+        store_q(qnext, rt, ct, xs[rt][ct]);
       }
     }
     alive = group_sync(ctr, (unsigned)((s + 2) * a.nb), local, abort_flag, a.status, &s_flag);
@@ -483,8 +528,8 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
   for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) {
-      const int i = row0 + rt * 16 + 4 * (lane >> 4);
-      const int r = col0 + ct * 16 + (lane & 15);
+      const int i = row0 + er(rt, ct);
+      const int r = col0 + ec(ct);
       const size_t o = (size_t)r * a.np + i;
       *reinterpret_cast<v4f*>(a.x + o) = v4f{xs[rt][ct][0], xs[rt][ct][1], xs[rt][ct][2], xs[rt][ct][3]};
       *reinterpret_cast<v4f*>(a.y + o) = v4f{ys[rt][ct][0], ys[rt][ct][1], ys[rt][ct][2], ys[rt][ct][3]};
@@ -492,11 +537,15 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
     }
 }
 
-template <int FORM, bool DISC, bool TANG = false>
+template <int FORM, bool DISC, bool TANG = false, bool LJ = false>
 __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
   __shared__ int s_flag;
   __shared__ int s_local;
-  steps_tile<FORM, DISC, TANG, 64>(a, (int)(blockIdx.x % a.groups), (int)(blockIdx.x / a.groups), s_flag, s_local);
+  // LJ: the workgroup's 64 rows of J in LDS, 64 np bytes (int8, FIX16) or 32 np (FP4, FP8)
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds_j[];
+  steps_tile<FORM, DISC, TANG, 64, LJ>(a, (int)(blockIdx.x % a.groups), (int)(blockIdx.x / a.groups), s_flag,
+                                       s_local, LJ ? lds_j : nullptr,
+                                       LJ ? (FORM == kFormFIX16 ? 64 : 32) * a.np : 0);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -768,9 +817,9 @@ __global__ void k_encode_j(const float* j32, int np, uint8_t* jf) {
       const int lanep = (i & 15) + 16 * (kk >> 5);
       const size_t off = ((size_t)(rt * nks + kc) * 2 + ((kk & 31) >> 4)) * 1024 + lanep * 16 + (kk & 15);
       jf[off] = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xFF);
-    } else if constexpr (FORM == kFormFIX16) {  // int8 J (entries in {0, +-1})
-      const int lanep = (i & 15) + 16 * ((kk & 63) >> 4);
-      const size_t off = ((size_t)(rt * nks + kc) * 2 + (kk >> 6)) * 1024 + lanep * 16 + (kk & 15);
+    } else if constexpr (FORM == kFormFIX16) {  // int8 J (entries in {0, +-1}), 32x32x32 A layout
+      const int lanep = (i & 31) + 32 * ((kk & 31) >> 4);
+      const size_t off = ((size_t)((i >> 5) * nks + kc) * 4 + (kk >> 5)) * 1024 + lanep * 16 + (kk & 15);
       jf[off] = (uint8_t)(int8_t)(int)v;
     } else if constexpr (FORM == kFormBF16X2) {
       const int lanep = (i & 15) + 16 * ((kk & 31) >> 3);
@@ -1174,13 +1223,26 @@ const void* steps_kernel() {
   return reinterpret_cast<const void*>(&k_steps<FORM, DISC>);
 }
 
+// The generic tile keeps its 64 rows of J in LDS when they fit beside the kernel's few
+// static bytes: int8 J (FIX16, 64 np bytes) or FP4 J (FP8, 32 np bytes).
+constexpr size_t kJLdsMax = 159 * 1024;
+size_t steps_lds_bytes(int form, int kind, int np) {
+  if (kind != kKindGeneric) return 0;
+  const size_t bytes = form == kFormFIX16 ? (size_t)64 * np : (form == kFormFP8 ? (size_t)32 * np : 0);
+  return bytes <= kJLdsMax ? bytes : 0;
+}
+
 template <bool DISC>
 const void* steps_kernel_disc(int form, int kind, int np) {
   if (kind == kKindRegJ) return steps_kernel_rj(np / kKS, DISC);
   switch (form) {
-    case kFormFP8: return steps_kernel<kFormFP8, DISC>();
+    case kFormFP8:
+      return steps_lds_bytes(form, kind, np) ? reinterpret_cast<const void*>(&k_steps<kFormFP8, DISC, false, true>)
+                                             : steps_kernel<kFormFP8, DISC>();
     case kFormBF16X2: return steps_kernel<kFormBF16X2, DISC>();
-    case kFormFIX16: return steps_kernel<kFormFIX16, DISC>();
+    case kFormFIX16:
+      return steps_lds_bytes(form, kind, np) ? reinterpret_cast<const void*>(&k_steps<kFormFIX16, DISC, false, true>)
+                                             : steps_kernel<kFormFIX16, DISC>();
     default: return steps_kernel<kFormFP32, DISC>();
   }
 }
@@ -1191,13 +1253,6 @@ const void* steps_kernel_for(int form, int kind, int np, bool discrete) {
   return discrete ? steps_kernel_disc<true>(form, kind, np) : steps_kernel_disc<false>(form, kind, np);
 }
 
-size_t steps_lds_bytes(int form, int kind, int np) {
-  (void)form;
-  const int nks = np / kKS;
-  (void)nks;
-  (void)kind;
-  return 0;
-}
 
 }  // namespace
 
