@@ -374,6 +374,26 @@ gsb_status gsb_batch_plan(int32_t units, const int32_t* width, const int32_t* ga
  * stream and synchronises the device.  out: host.  Errors: EINVAL, EDEVICE. */
 gsb_status gsb_device_ceilings(double* out, int32_t count);
 
+/* Encode `count` binary32 values as the operand of the coupling product sum_j J_ij x_j
+ * of eq. (3) sees them in precision `precision`, with the encoders the step kernels
+ * use for their operand stores.  discrete != 0 encodes the sign s(x) (+1 for x >= 0,
+ * including -0.0) instead, the dSB/GdSB operand (Sec. VI).  Output, value-major:
+ *   GSB_PREC_FP8    : count OCP E4M3 bytes (round to nearest, ties to even)
+ *   GSB_PREC_BF16X2 : count bfloat16 hi, then count bfloat16 lo, with hi = bf16(x) and
+ *                     lo = bf16(x - hi), both rounded to nearest even
+ *   GSB_PREC_FIX16  : count int8 hi, then count int8 lo, with rint(x 2^14) = 256 hi + lo
+ *                     (16-bit fixed point, the JX module's precision class, App. C)
+ *   GSB_PREC_FP32   : count binary32 values
+ * The value the product uses is the decoded sum (hi + lo, or (256 hi + lo) 2^-14).  For
+ * |x| <= 1, the range the wall of eq. (5) keeps x in, every form is defined; FIX16 needs
+ * |x| <= 1.  x, out: device pointers, 4-byte aligned, not overlapping; out holds count
+ * bytes (FP8), 4 count (BF16X2, FP32) or 2 count (FIX16).  Asynchronous on `stream`
+ * (hipStream_t, NULL = the null stream); allocates nothing.  count = 0 returns GSB_OK
+ * without touching the device.  Errors: EINVAL (precision, count < 0, NULL or misaligned
+ * pointers), EDEVICE. */
+gsb_status gsb_encode_operand(int32_t precision, int32_t discrete, const float* x, int64_t count, void* out,
+                              void* stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* gsb_last_error(void);
 

@@ -71,6 +71,8 @@ def _load():
     lib.orc_e4m3_encode_array.argtypes = [vp, vp, i64]
     lib.orc_bf16_round_array.restype = None
     lib.orc_bf16_round_array.argtypes = [vp, vp, i64]
+    lib.orc_operand_array.restype = None
+    lib.orc_operand_array.argtypes = [vp, vp, i64, i32, i32]
     for name in ("orc_run_f64", "orc_run_f32"):
         f = getattr(lib, name)
         f.restype = i32
@@ -153,6 +155,15 @@ def bf16_round(v: np.ndarray) -> np.ndarray:
 
 def fix16_round(v: float) -> float:
     return float(_load().orc_fix16_round(v))
+
+
+def operand(v: np.ndarray, form: int, discrete: bool = False) -> np.ndarray:
+    """Value the coupling product of eq. (3) uses for each binary32 x (float64 out): the
+    rounding of `form`, or the sign s(x) (+1 for x >= 0) of the dSB/GdSB product."""
+    v = np.ascontiguousarray(v, dtype=np.float32)
+    out = np.empty(v.shape, dtype=np.float64)
+    _load().orc_operand_array(_p(v), _p(out), v.size, int(discrete), form)
+    return out
 
 
 # ---- dynamics ----------------------------------------------------------------------------

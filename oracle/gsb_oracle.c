@@ -558,7 +558,14 @@ void orc_e4m3_round_array(const double* in, double* out, int64_t count) {
   for (int64_t k = 0; k < count; ++k) out[k] = orc_e4m3_round(in[k]);
 }
 void orc_e4m3_encode_array(const float* in, uint8_t* out, int64_t count) {
+#pragma omp parallel for schedule(static)
   for (int64_t k = 0; k < count; ++k) out[k] = orc_e4m3_encode((double)in[k]);
+}
+/* The value the coupling product of eq. (3) uses for each x: the operand form's rounding,
+ * or the sign s(x) for the dSB/GdSB product (Sec. VI). */
+void orc_operand_array(const float* in, double* out, int64_t count, int discrete, int form) {
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < count; ++k) out[k] = operand((double)in[k], discrete, form);
 }
 void orc_bf16_round_array(const float* in, float* out, int64_t count) {
   for (int64_t k = 0; k < count; ++k) out[k] = orc_bf16_round(in[k]);

@@ -354,6 +354,22 @@ gsb_status gsb_device_ceilings(double* out, int32_t count) {
   HIP_TRY(measure_ceilings(out, count), "ceiling probes");
   return GSB_OK;
 }
+gsb_status gsb_encode_operand(int32_t precision, int32_t discrete, const float* x, int64_t count, void* out,
+                              void* stream) {
+  g_err.clear();
+  if (precision < GSB_PREC_FP32 || precision > GSB_PREC_FIX16) return fail(GSB_EINVAL, "unknown precision");
+  if (count < 0) return fail(GSB_EINVAL, "count must be >= 0");
+  if (count == 0) return GSB_OK;
+  if (!x || !out) return fail(GSB_EINVAL, "x and out must be device pointers");
+  if (((uintptr_t)x & 3u) != 0 || ((uintptr_t)out & 3u) != 0) return fail(GSB_EINVAL, "x and out must be 4-byte aligned");
+  const size_t bytes = (size_t)count * (size_t)(precision == GSB_PREC_FP8 ? 1 : precision == GSB_PREC_FIX16 ? 2 : 4);
+  const uintptr_t xb = (uintptr_t)x, xe = xb + (size_t)count * 4, ob = (uintptr_t)out, oe = ob + bytes;
+  if (xb < oe && ob < xe) return fail(GSB_EINVAL, "x and out overlap");
+  HIP_TRY(launch_encode_operand(form_of(precision), discrete != 0, x, (size_t)count, out,
+                                static_cast<hipStream_t>(stream)),
+          "operand encoder launch");
+  return GSB_OK;
+}
 const char* gsb_version(void) { return "gsb-mi355x 0.1 (gfx950)"; }
 
 gsb_status gsb_create(const float* J, const float* h, int32_t n, gsb_ctx** out) {

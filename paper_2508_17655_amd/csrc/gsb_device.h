@@ -93,56 +93,80 @@ __device__ __forceinline__ bool group_sync(unsigned* ctr, unsigned target, int l
 // store_operand receives the 16x16 tile origin (ibase, rcol) of the lane's elements, or
 // for FIX16 the lane's own first element (row ibase, ibase % 4 == 0, column rcol).
 // ---------------------------------------------------------------------------------------
+// Encodings of four operand values (one lane's four rows), shared by the step kernels'
+// operand stores and by the standalone encoder.  `discrete` replaces each value by its
+// sign, s(x) = +1 for x >= 0 (including -0.0).
+__device__ __forceinline__ float operand_value(float x, bool discrete) {
+  return discrete ? (x < 0.0f ? -1.0f : 1.0f) : x;
+}
+// FP8: OCP E4M3 bytes, value v in byte v (round to nearest even, the hardware conversion).
+template <bool DISC>
+__device__ __forceinline__ unsigned encode_fp8x4(const float xv[4]) {
+  if constexpr (DISC) {
+    unsigned w = 0x38383838u;  // +1.0 in E4M3 in every byte, sign bits from x
+    w |= (xv[0] < 0.0f ? 0x80u : 0u) | (xv[1] < 0.0f ? 0x8000u : 0u) | (xv[2] < 0.0f ? 0x800000u : 0u) |
+         (xv[3] < 0.0f ? 0x80000000u : 0u);
+    return w;
+  } else {
+    int lo = __builtin_amdgcn_cvt_pk_fp8_f32(xv[0], xv[1], 0, false);
+    return (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(xv[2], xv[3], lo, true);
+  }
+}
+// BF16X2: hi = bf16(q), lo = bf16(q - hi) (q - hi is exact in binary32); two bf16 per word.
+template <bool DISC>
+__device__ __forceinline__ void encode_bf16x4(const float xv[4], v2u& wh, v2u& wl) {
+  unsigned short hi[4], lo[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const float q = operand_value(xv[v], DISC);
+    const __bf16 h = (__bf16)q;
+    const float hf = (float)h;
+    const __bf16 l = (__bf16)(q - hf);
+    hi[v] = __builtin_bit_cast(unsigned short, h);
+    lo[v] = __builtin_bit_cast(unsigned short, l);
+  }
+  wh = v2u{(unsigned)hi[0] | ((unsigned)hi[1] << 16), (unsigned)hi[2] | ((unsigned)hi[3] << 16)};
+  wl = v2u{(unsigned)lo[0] | ((unsigned)lo[1] << 16), (unsigned)lo[2] | ((unsigned)lo[3] << 16)};
+}
+// FIX16: q = rint(x 2^14) (exact scaling, round half to even) = 256 hi + lo with
+// hi = (q + 128) >> 8 in [-64, 64] and lo in [-128, 127]; int8 value v in byte v.
+template <bool DISC>
+__device__ __forceinline__ void encode_fix16x4(const float xv[4], unsigned& wh, unsigned& wl) {
+  wh = 0;
+  wl = 0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int qi = (int)__builtin_rintf(operand_value(xv[v], DISC) * 16384.0f);
+    const int hi = (qi + 128) >> 8;
+    const int lo = qi - 256 * hi;
+    wh |= (unsigned)(hi & 0xFF) << (8 * v);
+    wl |= (unsigned)(lo & 0xFF) << (8 * v);
+  }
+}
+
 template <int FORM, bool DISC>
 __device__ __forceinline__ void store_operand(uint8_t* qbuf, size_t plane_bytes, int nks,
                                               int ibase, int rcol, int lane, const float xv[4]) {
-  constexpr bool discrete = DISC;
   const int rb = rcol >> 4;
   const int kc = ibase >> 7;
   const int kk0 = (ibase & 127) + 4 * (lane >> 4);  // first of this lane's 4 rows
   if constexpr (FORM == kFormFP8) {
-    unsigned w;
-    if constexpr (discrete) {
-      w = 0x38383838u;  // +1.0 in E4M3 in every byte
-      w |= (xv[0] < 0.0f ? 0x80u : 0u) | (xv[1] < 0.0f ? 0x8000u : 0u) |
-           (xv[2] < 0.0f ? 0x800000u : 0u) | (xv[3] < 0.0f ? 0x80000000u : 0u);
-    } else {
-      int lo = __builtin_amdgcn_cvt_pk_fp8_f32(xv[0], xv[1], 0, false);
-      w = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(xv[2], xv[3], lo, true);
-    }
+    const unsigned w = encode_fp8x4<DISC>(xv);
     const int lanep = (lane & 15) + 16 * (kk0 >> 5);
     const int half = (kk0 & 31) >> 4;
     const size_t off = ((size_t)(rb * nks + kc) * 2 + half) * 1024 + lanep * 16 + (kk0 & 15);
     *reinterpret_cast<unsigned*>(qbuf + off) = w;
   } else if constexpr (FORM == kFormBF16X2) {
-    unsigned short hi[4], lo[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      float q = discrete ? (xv[v] < 0.0f ? -1.0f : 1.0f) : xv[v];
-      __bf16 h = (__bf16)q;
-      float hf = (float)h;
-      __bf16 l = (__bf16)(q - hf);  // q - hf is exact in binary32
-      hi[v] = __builtin_bit_cast(unsigned short, h);
-      lo[v] = __builtin_bit_cast(unsigned short, l);
-    }
+    v2u wh, wl;
+    encode_bf16x4<DISC>(xv, wh, wl);
     const int sub = kk0 >> 5;
     const int lanep = (lane & 15) + 16 * ((kk0 & 31) >> 3);
     const size_t off = ((size_t)(rb * nks + kc) * 4 + sub) * 1024 + lanep * 16 + (kk0 & 7) * 2;
-    v2u wh{(unsigned)hi[0] | ((unsigned)hi[1] << 16), (unsigned)hi[2] | ((unsigned)hi[3] << 16)};
-    v2u wl{(unsigned)lo[0] | ((unsigned)lo[1] << 16), (unsigned)lo[2] | ((unsigned)lo[3] << 16)};
     *reinterpret_cast<v2u*>(qbuf + off) = wh;
     *reinterpret_cast<v2u*>(qbuf + plane_bytes + off) = wl;
   } else if constexpr (FORM == kFormFIX16) {
-    unsigned wh = 0, wl = 0;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const float q = discrete ? (xv[v] < 0.0f ? -1.0f : 1.0f) : xv[v];
-      const int qi = (int)__builtin_rintf(q * 16384.0f);  // exact scaling, round half to even
-      const int hi = (qi + 128) >> 8;
-      const int lo = qi - 256 * hi;
-      wh |= (unsigned)(hi & 0xFF) << (8 * v);
-      wl |= (unsigned)(lo & 0xFF) << (8 * v);
-    }
+    unsigned wh, wl;
+    encode_fix16x4<DISC>(xv, wh, wl);
     (void)kk0;
     (void)rb;
     const int lanep = (rcol & 31) + 32 * ((ibase & 31) >> 4);
@@ -153,7 +177,7 @@ __device__ __forceinline__ void store_operand(uint8_t* qbuf, size_t plane_bytes,
   } else {
     v4f q;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) q[v] = discrete ? (xv[v] < 0.0f ? -1.0f : 1.0f) : xv[v];
+    for (int v = 0; v < 4; ++v) q[v] = operand_value(xv[v], DISC);
     const int grp = kk0 >> 4;
     const int lanep = (lane & 15) + 16 * ((kk0 & 15) >> 2);
     const size_t off = ((size_t)(rb * nks + kc) * 8 + grp) * 1024 + lanep * 16;

@@ -848,6 +848,48 @@ __global__ void k_encode_j4(const float* j32, int np, uint8_t* jf) {
   }
 }
 
+// x (count binary32 values) -> the operand encoding of FORM, value-major planes:
+//   FP8    : count E4M3 bytes
+//   BF16X2 : count bf16 hi, then count bf16 lo
+//   FIX16  : count int8 hi, then count int8 lo (rint(x 2^14) = 256 hi + lo)
+//   FP32   : count binary32 values
+// Four values per thread through the encoders of the step kernels' operand stores; the
+// values past `count` in the last group are zeros and are not stored.
+template <int FORM, bool DISC>
+__global__ void k_encode_operand(const float* x, size_t count, uint8_t* out) {
+  const size_t groups = (count + 3) / 4;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < groups; t += (size_t)gridDim.x * blockDim.x) {
+    const size_t e0 = 4 * t;
+    const int nv = count - e0 >= 4 ? 4 : (int)(count - e0);
+    float xv[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) xv[v] = v < nv ? x[e0 + v] : 0.0f;
+    if constexpr (FORM == kFormFP8) {
+      const unsigned w = encode_fp8x4<DISC>(xv);
+      for (int v = 0; v < nv; ++v) out[e0 + v] = (uint8_t)(w >> (8 * v));
+    } else if constexpr (FORM == kFormBF16X2) {
+      v2u wh, wl;
+      encode_bf16x4<DISC>(xv, wh, wl);
+      unsigned short* hi = reinterpret_cast<unsigned short*>(out);
+      unsigned short* lo = hi + count;
+      for (int v = 0; v < nv; ++v) {
+        hi[e0 + v] = (unsigned short)(wh[v >> 1] >> (16 * (v & 1)));
+        lo[e0 + v] = (unsigned short)(wl[v >> 1] >> (16 * (v & 1)));
+      }
+    } else if constexpr (FORM == kFormFIX16) {
+      unsigned wh, wl;
+      encode_fix16x4<DISC>(xv, wh, wl);
+      for (int v = 0; v < nv; ++v) {
+        out[e0 + v] = (uint8_t)(wh >> (8 * v));
+        out[count + e0 + v] = (uint8_t)(wl >> (8 * v));
+      }
+    } else {
+      float* q = reinterpret_cast<float*>(out);
+      for (int v = 0; v < nv; ++v) q[e0 + v] = operand_value(xv[v], DISC);
+    }
+  }
+}
+
 // SplitMix64 (Steele, Lea, Flood 2014): output k (k >= 1) of the generator seeded with s
 // is mix(s + k * 0x9E3779B97F4A7C15).
 __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
@@ -1274,6 +1316,21 @@ hipError_t launch_encode_j(int form, bool fp4, const float* j32, int np, void* j
   else if (form == kFormBF16X2) hipLaunchKernelGGL(k_encode_j<kFormBF16X2>, grid, block, 0, stream, j32, np, out);
   else if (form == kFormFIX16) hipLaunchKernelGGL(k_encode_j<kFormFIX16>, grid, block, 0, stream, j32, np, out);
   else hipLaunchKernelGGL(k_encode_j<kFormFP32>, grid, block, 0, stream, j32, np, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_operand(int form, bool discrete, const float* x, size_t count, void* out,
+                                 hipStream_t stream) {
+  const dim3 grid(grid_for((count + 3) / 4, 256)), block(256);
+  uint8_t* o = static_cast<uint8_t*>(out);
+  if (form == kFormFP8 && discrete) hipLaunchKernelGGL((k_encode_operand<kFormFP8, true>), grid, block, 0, stream, x, count, o);
+  else if (form == kFormFP8) hipLaunchKernelGGL((k_encode_operand<kFormFP8, false>), grid, block, 0, stream, x, count, o);
+  else if (form == kFormBF16X2 && discrete) hipLaunchKernelGGL((k_encode_operand<kFormBF16X2, true>), grid, block, 0, stream, x, count, o);
+  else if (form == kFormBF16X2) hipLaunchKernelGGL((k_encode_operand<kFormBF16X2, false>), grid, block, 0, stream, x, count, o);
+  else if (form == kFormFIX16 && discrete) hipLaunchKernelGGL((k_encode_operand<kFormFIX16, true>), grid, block, 0, stream, x, count, o);
+  else if (form == kFormFIX16) hipLaunchKernelGGL((k_encode_operand<kFormFIX16, false>), grid, block, 0, stream, x, count, o);
+  else if (discrete) hipLaunchKernelGGL((k_encode_operand<kFormFP32, true>), grid, block, 0, stream, x, count, o);
+  else hipLaunchKernelGGL((k_encode_operand<kFormFP32, false>), grid, block, 0, stream, x, count, o);
   return hipGetLastError();
 }
 

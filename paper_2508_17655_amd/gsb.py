@@ -43,7 +43,7 @@ SYMBOLS = ("gsb_create", "gsb_destroy", "gsb_set", "gsb_get", "gsb_set_stream", 
            "gsb_batch_create", "gsb_batch_destroy", "gsb_batch_set_stream", "gsb_batch_workspace_size",
            "gsb_batch_bind_workspace", "gsb_batch_set_coupling", "gsb_batch_set", "gsb_batch_get", "gsb_batch_autotune",
            "gsb_batch_run", "gsb_batch_energy", "gsb_batch_best", "gsb_batch_state", "gsb_batch_last_ms",
-           "gsb_batch_plan", "gsb_device_ceilings", "gsb_last_error", "gsb_version")
+           "gsb_batch_plan", "gsb_device_ceilings", "gsb_encode_operand", "gsb_last_error", "gsb_version")
 
 
 class GsbError(RuntimeError):
@@ -108,6 +108,7 @@ def load_library(path: str = LIB_PATH):
         "gsb_batch_last_ms": (i32, [vp, ctypes.POINTER(dbl)]),
         "gsb_batch_plan": (i32, [i32, vp, vp, vp, i32, i32, vp, vp]),
         "gsb_device_ceilings": (i32, [vp, i32]),
+        "gsb_encode_operand": (i32, [i32, i32, vp, ctypes.c_int64, vp, vp]),
         "gsb_last_error": (ctypes.c_char_p, []),
         "gsb_version": (ctypes.c_char_p, []),
     }
@@ -378,6 +379,40 @@ def gsb_device_ceilings() -> dict:
     out = np.zeros(len(CEILING_NAMES), dtype=np.float64)
     _check(load_library().gsb_device_ceilings(_ptr(out), out.size), "gsb_device_ceilings")
     return dict(zip(CEILING_NAMES, (float(v) for v in out)))
+
+
+def gsb_encode_operand(precision: int, discrete: int, x_ptr: int | None, count: int, out_ptr: int | None,
+                       stream: int | None) -> None:
+    _check(load_library().gsb_encode_operand(precision, discrete, ctypes.c_void_p(x_ptr or 0), count,
+                                             ctypes.c_void_p(out_ptr or 0), ctypes.c_void_p(stream or 0)),
+           "gsb_encode_operand")
+
+
+def encode_operand(x, precision: int, discrete: bool = False):
+    """The operand of the coupling product for the binary32 device tensor x (1-D), as the
+    step kernels encode it: FP8 -> uint8 E4M3 codes; BF16X2 -> (hi, lo) bfloat16;
+    FIX16 -> (hi, lo) int8 with rint(x 2^14) = 256 hi + lo; FP32 -> float32.  Runs on
+    PyTorch's current stream."""
+    import torch
+    if x.dtype != torch.float32 or x.dim() != 1 or not x.is_cuda:
+        raise ValueError("x must be a 1-D float32 device tensor")
+    x = x.contiguous()
+    n = x.numel()
+    if precision == GSB_PREC_FP8:
+        out = torch.empty(n, dtype=torch.uint8, device=x.device)
+    elif precision == GSB_PREC_BF16X2:
+        out = torch.empty((2, n), dtype=torch.int16, device=x.device)
+    elif precision == GSB_PREC_FIX16:
+        out = torch.empty((2, n), dtype=torch.int8, device=x.device)
+    else:
+        out = torch.empty(n, dtype=torch.float32, device=x.device)
+    gsb_encode_operand(precision, int(discrete), x.data_ptr(), n, out.data_ptr(),
+                       torch.cuda.current_stream().cuda_stream)
+    if precision == GSB_PREC_BF16X2:
+        return out[0].view(torch.bfloat16), out[1].view(torch.bfloat16)
+    if precision == GSB_PREC_FIX16:
+        return out[0], out[1]
+    return out
 
 
 class Batch:

@@ -77,6 +77,21 @@ def test_options_and_errors_without_device():
         gsb.gsb_destroy(ctx)
 
 
+def test_encode_operand_arguments_are_checked_before_any_device_work():
+    enc = gsb.gsb_encode_operand
+    assert _status(enc, 7, 0, 0x1000, 4, 0x2000, None) == gsb.GSB_EINVAL      # precision
+    assert _status(enc, gsb.GSB_PREC_FP8, 0, 0x1000, -1, 0x2000, None) == gsb.GSB_EINVAL
+    assert _status(enc, gsb.GSB_PREC_FP8, 0, None, 4, 0x2000, None) == gsb.GSB_EINVAL
+    assert _status(enc, gsb.GSB_PREC_FP8, 0, 0x1000, 4, None, None) == gsb.GSB_EINVAL
+    assert _status(enc, gsb.GSB_PREC_FP8, 0, 0x1002, 4, 0x2000, None) == gsb.GSB_EINVAL  # misaligned
+    assert _status(enc, gsb.GSB_PREC_FP8, 0, 0x1000, 4, 0x2001, None) == gsb.GSB_EINVAL
+    # out overlapping x: FP8 needs count bytes, FP32 4 count bytes
+    assert _status(enc, gsb.GSB_PREC_FP32, 0, 0x1000, 16, 0x1020, None) == gsb.GSB_EINVAL
+    assert _status(enc, gsb.GSB_PREC_FP8, 0, 0x1000, 16, 0x0ff4, None) == gsb.GSB_EINVAL
+    # count 0 is a no-op that never touches the device
+    enc(gsb.GSB_PREC_FIX16, 0, None, 0, None, None)
+
+
 @pytest.mark.parametrize("n", [2, 9, 64])
 def test_eigenvalues_and_default_c(n):
     # App. A: c = 1/lambda_max; eq. (13) dt = 1.25 sqrt(2/(1 - lambda_min/lambda_max)).
