@@ -40,6 +40,31 @@ def tts99(t_com: float, p_run: float) -> float:
     return t_com * math.log(0.01) / math.log(1.0 - p_run)
 
 
+def tts_vs_replicas(g8, rows, sizes=(16, 128, 1024, 4096), reps=3):
+    """TTS99 with the batch semantics (Sec. VI) for launches of R replicas of the FP8 form:
+    T_com(R) is the measured wall time of one launch (run + best), P_S of the launch is
+    1 - (1 - p_hat)^R with the per-replica p_hat measured at R = 1024."""
+    import torch
+    out = []
+    for row in rows:
+        for r in sizes:
+            g8.run(row["variant"], A=row["A"], dt=DT, replicas=r, steps=M, seed=7000)
+            g8.best()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for s in range(reps):
+                g8.run(row["variant"], A=row["A"], dt=DT, replicas=r, steps=M, seed=7001 + s)
+                g8.best()
+            torch.cuda.synchronize()
+            t_com = (time.perf_counter() - t0) / reps
+            p_run = 1.0 - (1.0 - row["p_hat"]) ** r
+            out.append({"variant": row["variant"], "A": row["A"], "replicas": r, "p_hat": row["p_hat"],
+                        "t_com_s": t_com, "us_per_step": 1e6 * t_com / M,
+                        "replica_spin_steps_per_s": r * N * M / t_com, "p_run": p_run,
+                        "tts99_s": _finite(tts99(t_com, p_run))})
+    return out
+
+
 def _finite(v: float):
     return v if math.isfinite(v) else None
 
@@ -438,6 +463,7 @@ def main():
                           "tts_semantics": "T_com = one launch of all replicas; P_S of the batch = 1-(1-p_hat)^R",
                           "best_gbsb": best_row, "table": table}
         out["tts99_s"] = best_row["fp8"]["tts99_s"]
+        out["success"]["tts_vs_replicas"] = tts_vs_replicas(g8, [best_row["fp8"], table[0]])
     if not args.no_chaos:
         out["chaos"] = chaos_sweeps(J, c)
     if not args.no_batch:

@@ -72,6 +72,8 @@ def test_tts_definition():
     assert bench.tts99(3.0, 0.995) == 3.0          # P_S above the target: one run
     assert bench.tts99(3.0, 1.0) == 3.0
     assert bench.tts99(3.0, 0.0) == math.inf
+    # P_S = 0.5: ln(0.01)/ln(0.5) = 6.644 runs
+    assert bench.tts99(1.0, 0.5) == pytest.approx(6.6439, abs=1e-4)
     # P_S = 1 - (1 - 0.99)^(1/k) needs exactly k runs: 1 - (1 - P_S)^k = 0.99
     for k in (2, 5, 40):
         ps = 1 - (1 - p99) ** (1 / k)
