@@ -81,7 +81,9 @@ __device__ __forceinline__ bool group_sync(unsigned* ctr, unsigned target, int l
 // 1 KiB load per VGPR quad:
 //   FP8   : 2048 B = [half 2][lane 64][16 B];  lane = r%16 + 16*(kk/32),
 //           byte 16*half + b  <->  kk = 32*(lane/16) + 16*half + b            (16x16x128)
-//   BF16  : 4096 B per plane = [sub 4][lane 64][8 bf16]; kk = 32*sub + 8*(lane/16) + e
+//   BF16  : 32x32x16 bf16 MFMA.  Per (32-replica block, k-step): 8 KiB per plane =
+//           [sixteenth 8][lane 64][8 bf16]; lane = r%32 + 32*((kk%16)/8),
+//           kk = 16*sixteenth + 8*(lane/32) + e; plane 0 holds hi, plane 1 lo.
 //   FP32  : 8192 B = [grp 8][lane 64][4 f32];  kk = 16*grp + 4*(lane/16) + t, where
 //           element t feeds the t-th of four 16x16x4 MFMAs of that group.
 //   FIX16 : 32x32x32 int8 MFMA.  Per (32-replica block, k-step): 4 KiB per plane =
@@ -91,7 +93,8 @@ __device__ __forceinline__ bool group_sync(unsigned* ctr, unsigned target, int l
 //           per (32-row tile, k-step), rows in place of replicas.
 // (kk = k mod 128.)  J uses the same layouts with the row i in place of the replica r.
 // store_operand receives the 16x16 tile origin (ibase, rcol) of the lane's elements, or
-// for FIX16 the lane's own first element (row ibase, ibase % 4 == 0, column rcol).
+// for the 32x32 layouts (BF16, FIX16) the lane's own first element (row ibase,
+// ibase % 4 == 0, column rcol).
 // ---------------------------------------------------------------------------------------
 // Encodings of four operand values (one lane's four rows), shared by the step kernels'
 // operand stores and by the standalone encoder.  `discrete` replaces each value by its
@@ -159,9 +162,11 @@ __device__ __forceinline__ void store_operand(uint8_t* qbuf, size_t plane_bytes,
   } else if constexpr (FORM == kFormBF16X2) {
     v2u wh, wl;
     encode_bf16x4<DISC>(xv, wh, wl);
-    const int sub = kk0 >> 5;
-    const int lanep = (lane & 15) + 16 * ((kk0 & 31) >> 3);
-    const size_t off = ((size_t)(rb * nks + kc) * 4 + sub) * 1024 + lanep * 16 + (kk0 & 7) * 2;
+    (void)kk0;
+    (void)rb;
+    const int lanep = (rcol & 31) + 32 * ((ibase & 15) >> 3);
+    const size_t off =
+        ((size_t)((rcol >> 5) * nks + kc) * 8 + ((ibase & 127) >> 4)) * 1024 + lanep * 16 + (ibase & 7) * 2;
     *reinterpret_cast<v2u*>(qbuf + off) = wh;
     *reinterpret_cast<v2u*>(qbuf + plane_bytes + off) = wl;
   } else if constexpr (FORM == kFormFIX16) {

@@ -105,10 +105,10 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
 
   // Elements of the wave's 64 x 32 tile held by this lane: rows row0 + er(rt, ct) + v
   // (v < 4) of column col0 + ec(ct).  With 16x16 MFMA tiles (4 x 2 of them) that is rows
-  // 16 rt + 4 (lane/16) + v of column 16 ct + lane%16; FIX16 uses 32x32 int8 tiles (2 x 1),
-  // whose lane holds rows 32 (g/4) + 8 (g%4) + 4 (lane/32) + v of column lane%32 for
-  // register group g = 2 rt + ct.
-  constexpr bool T32 = FORM == kFormFIX16;
+  // 16 rt + 4 (lane/16) + v of column 16 ct + lane%16; BF16X2 and FIX16 use 32x32 tiles
+  // (2 x 1), whose lane holds rows 32 (g/4) + 8 (g%4) + 4 (lane/32) + v of column lane%32
+  // for register group g = 2 rt + ct.
+  constexpr bool T32 = FORM == kFormFIX16 || FORM == kFormBF16X2;
   auto er = [&](int rt, int ct) {
     return T32 ? 32 * (rt >> 1) + 8 * ((2 * rt + ct) & 3) + 4 * (lane >> 5) : rt * 16 + 4 * (lane >> 4);
   };
@@ -287,61 +287,78 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
       }
       if (nks_l < nks) segment(nks_l, nks, load_a_glb, std::integral_constant<int, kPF - 1>{});
     } else if constexpr (FORM == kFormBF16X2) {
-      // hi and lo planes of x (the sign operand has no low part) against bf16 J, 16x16x32
-      // MFMAs with binary32 accumulation.  Software pipeline over quarter k-steps (32
-      // spins): Q fragments of both planes kPFs quarters ahead, J fragments one ahead;
-      // 4 nks is a multiple of kPFs and the last kPFs quarters are peeled without loads.
+      // hi and lo planes of x (the sign operand has no low part) against bf16 J on
+      // 32x32x16 MFMAs (the 16x16x32 shape runs at ~55% of their rate here), binary32
+      // accumulation, one accumulator per plane and 32-row tile; G = G_hi + G_lo.
+      // Software pipeline over sixteenth k-steps (16 spins, 2 or 4 MFMAs each): Q
+      // fragments kQS sixteenths ahead and J fragments kJS ahead, in register rings whose
+      // indices are compile-time constants.  8 nks is a multiple of kQS; the last kQS
+      // sixteenths are peeled without Q loads.
       constexpr int planes = DISC ? 1 : 2;
-      constexpr int kPFs = kKStepsUnroll;
-      const int nsub = 4 * nks;
-      v8bf aj[2][4];
-      v8bf bq[kPFs][planes][2];
+      constexpr int kQS = 2 * kKStepsUnroll;  // 8 sixteenths
+      constexpr int kJS = 3, kJR = 4;         // J distance and ring (kJR divides kQS)
+      typedef float v16f __attribute__((ext_vector_type(16)));
+      v16f facc[2][2];  // [plane][32-row tile]
+#pragma unroll
+      for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) facc[pl][t] = v16f{};
+      const int nsub = 8 * nks;
+      const int cb = col0 >> 5;  // the wave's 32-column block
+      v8bf aj[kJR][2];
+      v8bf bq[kQS][planes];
       auto load_a = [&](int sb, v8bf* dst) {
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
-          dst[rt] = *reinterpret_cast<const v8bf*>(jrows + ((size_t)(rt * nks + (sb >> 2)) * 4 + (sb & 3)) * 1024 +
-                                                   lane * 16);
+        for (int t = 0; t < 2; ++t)
+          dst[t] = *reinterpret_cast<const v8bf*>(jrows + ((size_t)(t * nks + (sb >> 3)) * 8 + (sb & 7)) * 1024 +
+                                                  lane * 16);
       };
-      auto load_b = [&](int sb, v8bf (*dst)[2]) {
+      auto load_b = [&](int sb, v8bf* dst) {
+#pragma unroll
+        for (int pl = 0; pl < planes; ++pl) {
+          const unsigned base =
+              (unsigned)(pl * plane_bytes + ((size_t)(cb * nks + (sb >> 3)) * 8 + (sb & 7)) * 1024 + lane * 16);
+          dst[pl] = __builtin_bit_cast(v8bf, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kQPolicy));
+        }
+      };
+      auto mfmas = [&](const v8bf* aa, const v8bf* bb) {
 #pragma unroll
         for (int pl = 0; pl < planes; ++pl)
 #pragma unroll
-          for (int ct = 0; ct < 2; ++ct) {
-            const unsigned base = (unsigned)(pl * plane_bytes + ((size_t)((rb0 + ct) * nks + (sb >> 2)) * 4 + (sb & 3)) *
-                                                                    1024 + lane * 16);
-            dst[pl][ct] = __builtin_bit_cast(v8bf, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kQPolicy));
-          }
-      };
-      auto mfmas = [&](const v8bf* aa, v8bf (*bb)[2]) {
-#pragma unroll
-        for (int pl = 0; pl < planes; ++pl)
-#pragma unroll
-          for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-            for (int ct = 0; ct < 2; ++ct)
-              acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aa[rt], bb[pl][ct], acc[rt][ct], 0, 0, 0);
+          for (int t = 0; t < 2; ++t)
+            facc[pl][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aa[t], bb[pl], facc[pl][t], 0, 0, 0);
       };
 #pragma unroll
-      for (int u = 0; u < kPFs; ++u) load_b(u, bq[u]);
-      load_a(0, aj[0]);
+      for (int u = 0; u < kQS; ++u) load_b(u, bq[u]);
+#pragma unroll
+      for (int d = 0; d < kJS; ++d) load_a(d, aj[d]);
       int s0 = 0;
-      for (; s0 < nsub - kPFs; s0 += kPFs) {
+      for (; s0 < nsub - kQS; s0 += kQS) {
 #pragma unroll
-        for (int u = 0; u < kPFs; ++u) {
-          load_a(s0 + u + 1, aj[(u + 1) & 1]);
+        for (int u = 0; u < kQS; ++u) {
+          load_a(s0 + u + kJS, aj[(u + kJS) % kJR]);  // < nsub: s0 <= nsub - 2 kQS
           __builtin_amdgcn_sched_barrier(0);
-          mfmas(aj[u & 1], bq[u]);
-          load_b(s0 + u + kPFs, bq[u]);
+          mfmas(aj[u % kJR], bq[u]);
+          load_b(s0 + u + kQS, bq[u]);
           __builtin_amdgcn_sched_barrier(0);
         }
       }
 #pragma unroll
-      for (int u = 0; u < kPFs; ++u) {
-        if (u + 1 < kPFs) load_a(s0 + u + 1, aj[(u + 1) & 1]);
+      for (int u = 0; u < kQS; ++u) {
+        if (u + kJS < kQS) load_a(s0 + u + kJS, aj[(u + kJS) % kJR]);
         __builtin_amdgcn_sched_barrier(0);
-        mfmas(aj[u & 1], bq[u]);
+        mfmas(aj[u % kJR], bq[u]);
         __builtin_amdgcn_sched_barrier(0);
       }
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int j = 4 * ((2 * rt + ct) & 3) + v;
+            acc[rt][ct][v] = planes == 2 ? facc[0][rt >> 1][j] + facc[planes - 1][rt >> 1][j] : facc[0][rt >> 1][j];
+          }
     } else if constexpr (FORM == kFormFIX16) {
       // two int8 passes (hi, lo planes; the sign operand has lo = 0) on 32x32x32 MFMAs
       // (the 16x16x64 shape runs at ~58% of their rate here), exact int32 sums;
@@ -821,9 +838,9 @@ __global__ void k_encode_j(const float* j32, int np, uint8_t* jf) {
       const int lanep = (i & 31) + 32 * ((kk & 31) >> 4);
       const size_t off = ((size_t)((i >> 5) * nks + kc) * 4 + (kk >> 5)) * 1024 + lanep * 16 + (kk & 15);
       jf[off] = (uint8_t)(int8_t)(int)v;
-    } else if constexpr (FORM == kFormBF16X2) {
-      const int lanep = (i & 15) + 16 * ((kk & 31) >> 3);
-      const size_t off = ((size_t)(rt * nks + kc) * 4 + (kk >> 5)) * 1024 + lanep * 16 + (kk & 7) * 2;
+    } else if constexpr (FORM == kFormBF16X2) {  // bf16 J, 32x32x16 A layout
+      const int lanep = (i & 31) + 32 * ((kk & 15) >> 3);
+      const size_t off = ((size_t)((i >> 5) * nks + kc) * 8 + (kk >> 4)) * 1024 + lanep * 16 + (kk & 7) * 2;
       *reinterpret_cast<__bf16*>(jf + off) = (__bf16)v;
     } else {
       const int lanep = (i & 15) + 16 * ((kk & 15) >> 2);
