@@ -97,6 +97,20 @@ def load_traffic(name: str):
     return d.get("hbm_bytes_per_launch")
 
 
+def load_mfma_busy(name: str):
+    """Fraction of SIMD-cycles the matrix cores were busy during the step kernel, from the
+    committed rocprofv3 counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", name)
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("mfma_busy_frac")
+
+
 def cpu_baseline(J, c, target_s: float = 12.0):
     """The oracle as it stands (strict binary32 update, E4M3 product, the FP8 form's
     arithmetic) on a bounded sample of the same run: all host threads, one replica each."""
@@ -433,6 +447,7 @@ def main():
         "fix16_form": fix16_form,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP8_PEAK / 1e12, "unit": "TFLOP/s",
                      "frac": achieved * 1e12 / FP8_PEAK, "traffic": load_traffic("k_steps_rj_fp8_n2000_r1024_counters.json"),
+                     "mfma_busy_frac_counters": load_mfma_busy("k_steps_rj_fp8_n2000_r1024_mfma_counters.json"),
                      "kernel": "k_steps_rj<16> (FP8 product, J resident in registers)", "kernel_ms_per_launch": k_ms,
                      "flop_per_launch": flop},
     }

@@ -184,6 +184,31 @@ def test_fp8_generic_kernel_bitexact(orc, variant):
     check_exact(E, orc.energy(J, orc.spins(x)), "energies")
 
 
+@pytest.mark.parametrize("precision,variant,form", [("fp8", "gbsb", "e4m3"), ("fix16", "gbsb", "fix16"),
+                                                     ("bf16x2", "gdsb", "exact"), ("fp32", "dsb", "exact")])
+def test_more_replicas_than_one_launch_holds(orc, precision, variant, form):
+    # At N = 2000 one co-resident launch holds 1024 replicas; 1100 replicas run as a
+    # launch of 1024 and one of 128 (76 of them padding).  Replicas on both sides of the
+    # split, and the last one, against the oracle.
+    n, R, M, A, seed = 2000, 1100, 40, 0.2, 77
+    say(f"case two launches precision={precision} variant={variant} n={n} R={R} M={M}")
+    J = instances.dense_pm1(n, 2)
+    c = instances.paper_c(n)
+    g = make(J, precision, c)
+    g.run(variant, A=A, dt=1.25, replicas=R, steps=M, seed=seed)
+    x, y, p, _ = g.state()
+    E = g.energy()
+    g.close()
+    assert x.shape == (R, n)
+    sample = np.array([0, 1023, 1024, 1077, R - 1])
+    x0, y0, p0 = oracle_start(orc, n, R, seed, orc.INIT_X)
+    f = {"e4m3": orc.FORM_E4M3, "fix16": orc.FORM_FIX16, "exact": orc.FORM_EXACT}[form]
+    xo, yo, po = orc.run(J, orc.VARIANTS[variant], A=A, dt=1.25, c=c, steps=M, x=x0[sample], y=y0[sample],
+                         p=p0[sample], form=f, mode="fp32")
+    check_exact(x[sample], xo, "x"); check_exact(y[sample], yo, "y"); check_exact(p[sample], po, "p")
+    check_exact(E, orc.energy(J, orc.spins(x)), "energies")
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16x2"])
 def test_continuous_forms_error_bounds(orc, precision):
     # bSB with a continuous product: one step from an identical state, and 100 steps.
