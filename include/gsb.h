@@ -95,8 +95,15 @@ typedef enum {
   GSB_OPT_STEP = 6,       /* read-only: current step index m of the run */
   GSB_OPT_REPLICAS = 7,   /* read-only: replicas of the current run */
   GSB_OPT_DT_STABLE = 8,  /* read-only: eq. (13) time step with D_t = 1.25 */
-  GSB_OPT_N_DYN = 9       /* read-only: spins carried by the dynamics (n, plus 1 with a
+  GSB_OPT_N_DYN = 9,      /* read-only: spins carried by the dynamics (n, plus 1 with a
                              field ancilla); the length of one replica in gsb_state */
+  GSB_OPT_STEP_KERNEL = 10 /* step kernel of the FP8 product at n_p <= 2048 (both keep J
+                             resident on chip, 256 spins x 32 replicas per workgroup, and
+                             compute the same bits): 0 = automatic (default), 1 = one wave
+                             per SIMD computes product and update (J in registers),
+                             2 = two waves per SIMD, one computing the product (J in
+                             registers and LDS), the other the update.  Other precisions
+                             and sizes ignore it.  Takes effect at the next gsb_init. */
 } gsb_option;
 
 /* Create a context for the instance (J, h).

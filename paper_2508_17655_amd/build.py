@@ -23,7 +23,7 @@ def build(verbose: bool = False) -> str:
     objs = []
     common = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-result"]
     for src, extra in (("gsb_kernels.hip", DEVICE_FLAGS), ("gsb_steps_rj.hip", DEVICE_FLAGS),
-                       ("gsb_probe.hip", DEVICE_FLAGS),
+                       ("gsb_steps_ws.hip", DEVICE_FLAGS), ("gsb_probe.hip", DEVICE_FLAGS),
                        ("gsb_api.cpp", ["-ffp-contract=off"]), ("gsb_batch.cpp", ["-ffp-contract=off"])):
         obj = os.path.join(CSRC, src + ".o")
         cmd = [HIPCC, *common, *extra, "-c", os.path.join(CSRC, src), "-o", obj]

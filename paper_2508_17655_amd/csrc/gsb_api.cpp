@@ -178,6 +178,7 @@ struct gsb_ctx {
   bool eig_done = false;
   int precision = GSB_PREC_FP32;
   int init_mode = GSB_INIT_X;
+  int kernel_pref = 0;  // GSB_OPT_STEP_KERNEL
   hipStream_t stream = nullptr;
   // run
   bool inited = false;
@@ -235,7 +236,7 @@ gsb_status plan(gsb_ctx* c, int R, int M, Layout* L, int* kind_out, bool tangent
   const int np = c->np;
   const int rp = (R + kRepPad - 1) / kRepPad * kRepPad;
   const int cols = tangent ? 2 * rp : rp;
-  const int kind = tangent ? (int)kKindGeneric : choose_kind(form, np);
+  const int kind = tangent ? (int)kKindGeneric : choose_kind(form, np, c->kernel_pref);
   const int bm = tile_rows_kind(kind), bn = tile_cols_kind(kind);
   int dev_count = 0;
   if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1)
@@ -456,6 +457,15 @@ gsb_status gsb_set(gsb_ctx* c, int32_t option, double v) {
       c->init_mode = mm;
       return GSB_OK;
     }
+    case GSB_OPT_STEP_KERNEL: {
+      const int k = (int)v;
+      if ((double)k != v || k < 0 || k > 2) return fail(GSB_EINVAL, "step kernel must be 0, 1 or 2");
+      if (k != c->kernel_pref) {
+        c->kernel_pref = k;
+        c->inited = false;  // the workspace layout follows the kernel
+      }
+      return GSB_OK;
+    }
     default:
       return fail(GSB_EINVAL, "unknown or read-only option " + std::to_string(option));
   }
@@ -475,6 +485,7 @@ gsb_status gsb_get(gsb_ctx* c, int32_t option, double* v) {
       return GSB_OK;
     case GSB_OPT_PRECISION: *v = c->precision; return GSB_OK;
     case GSB_OPT_INIT_MODE: *v = c->init_mode; return GSB_OK;
+    case GSB_OPT_STEP_KERNEL: *v = c->kernel_pref; return GSB_OK;
     case GSB_OPT_LAMBDA_MAX: ensure_eig(c); *v = c->lmax; return GSB_OK;
     case GSB_OPT_LAMBDA_MIN: ensure_eig(c); *v = c->lmin; return GSB_OK;
     case GSB_OPT_N: *v = c->n_user; return GSB_OK;

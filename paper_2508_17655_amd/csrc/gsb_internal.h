@@ -51,6 +51,8 @@ hipError_t launch_steps(int form, int kind, const StepArgs& a, hipStream_t strea
 int max_coresident_workgroups(int form, int kind, int np, bool tangent = false);
 // The register-resident FP8 kernel for nks = np / 128 in {4, 8, 12, 16}, else nullptr.
 const void* steps_kernel_rj(int nks, bool discrete);
+const void* steps_kernel_ws(int nks, bool discrete);
+size_t steps_ws_lds_bytes(int np);
 // Reverse pass of the binary32 dynamics over a recorded tape (see k_adjoint); a.x, a.y,
 // a.p carry the cotangents in and out.  Occupancy limit of that kernel.
 hipError_t launch_adjoint(const StepArgs& a, hipStream_t stream);
@@ -67,7 +69,7 @@ hipError_t launch_tangent_extract(int n, int np, int R, const float* x, const fl
                                   hipStream_t stream);
 // eq. (8) for pairs (2k, 2k + 1), k < pairs, over spins < n.
 hipError_t launch_delta(int n, int np, int pairs, const float* x, double* out, hipStream_t stream);
-int choose_kind(int form, int np);
+int choose_kind(int form, int np, int pref = 0);
 hipError_t launch_energy(const float* j32, int n, int np, int rp, int r_count, const float* x,
                          double* partial, double* energies, hipStream_t stream);
 size_t energy_partial_doubles(int np, int rp);

@@ -1286,6 +1286,7 @@ const void* steps_kernel() {
 // static bytes: int8 J (FIX16, 64 np bytes) or FP4 J (FP8, 32 np bytes).
 constexpr size_t kJLdsMax = 159 * 1024;
 size_t steps_lds_bytes(int form, int kind, int np) {
+  if (kind == kKindWaveSpec) return steps_ws_lds_bytes(np);
   if (kind != kKindGeneric) return 0;
   const size_t bytes = form == kFormFIX16 ? (size_t)64 * np : (form == kFormFP8 ? (size_t)32 * np : 0);
   return bytes <= kJLdsMax ? bytes : 0;
@@ -1294,6 +1295,7 @@ size_t steps_lds_bytes(int form, int kind, int np) {
 template <bool DISC>
 const void* steps_kernel_disc(int form, int kind, int np) {
   if (kind == kKindRegJ) return steps_kernel_rj(np / kKS, DISC);
+  if (kind == kKindWaveSpec) return steps_kernel_ws(np / kKS, DISC);
   switch (form) {
     case kFormFP8:
       return steps_lds_bytes(form, kind, np) ? reinterpret_cast<const void*>(&k_steps<kFormFP8, DISC, false, true>)
@@ -1358,8 +1360,9 @@ hipError_t launch_init_state(int n, int np, int rp, uint64_t seed, int mode, flo
   return hipGetLastError();
 }
 
-int choose_kind(int form, int np) {
-  return (form == kFormFP8 && np <= 2048) ? kKindRegJ : kKindGeneric;
+int choose_kind(int form, int np, int pref) {
+  if (form != kFormFP8 || np > 2048) return kKindGeneric;
+  return pref == 1 ? kKindRegJ : kKindWaveSpec;
 }
 
 int max_coresident_workgroups(int form, int kind, int np, bool tangent) {
@@ -1378,7 +1381,7 @@ int max_coresident_workgroups(int form, int kind, int np, bool tangent) {
     const size_t lds = steps_lds_bytes(form, kind, np);
     if (lds > 0 && hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
       return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kThreads, lds) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads_kind(kind), lds) != hipSuccess) return 0;
     best = disc == 0 ? per_cu * cus : std::min(best, per_cu * cus);
   }
   return best;
@@ -1413,7 +1416,8 @@ hipError_t launch_steps(int form, int kind, const StepArgs& a, hipStream_t strea
   }
   StepArgs copy = a;
   void* args[] = {&copy};
-  return hipLaunchCooperativeKernel(k, dim3(a.groups * a.nb), dim3(kThreads), args, (unsigned)lds, stream);
+  return hipLaunchCooperativeKernel(k, dim3(a.groups * a.nb), dim3(threads_kind(kind)), args, (unsigned)lds,
+                                    stream);
 }
 
 hipError_t launch_init_tangent(int n, int np, int rp, uint64_t seed, int mode, uint64_t tseed, float* x, float* y,

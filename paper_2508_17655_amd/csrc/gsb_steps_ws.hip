@@ -1,0 +1,371 @@
+// gsb_steps_ws.hip -- the wave-specialised step kernel of libgsb (gfx950): FP8 product,
+// J held as FP4 in the register files and LDS of the CUs for the whole launch
+// (np <= 2048), with the product and the update of eqs. (3)-(7) in different waves.
+//
+// Same tile as the register-resident kernel: workgroup (g, mb) owns spins
+// [256 mb, 256 mb + 256) of replicas [32 g, 32 g + 32), and row slice w (64 spins) of it
+// belongs to SIMD w.  Each SIMD runs two waves of the workgroup:
+//   - product wave w (waves 0-3): keeps its 64 rows of J (k-steps [0, NR) in registers,
+//     the rest in LDS), runs the K loops of both 16-replica column tiles, alternately,
+//     and leaves each 64 x 16 product in an LDS slot;
+//   - update wave w (waves 4-7): takes the product from the slot, applies eqs. (7), (3),
+//     (4), (5) in binary32 (one rounding per operator), writes the next operand and
+//     counts itself in at that column tile's group counter.
+// The matrix cores and the vector ALU of a SIMD execute instructions of different waves
+// at the same time, so the update of one column tile runs under the K loop of the other,
+// and no product wave waits at a barrier other than for its operand data.
+#include "gsb_device.h"
+
+#pragma clang fp contract(off)
+
+namespace gsb {
+namespace {
+
+constexpr int kWsThreads = 512;
+// k-steps of J per product wave in VGPRs; the rest sit in LDS.  The register budget of a
+// wave at two waves per SIMD is 256 VGPRs and AGPRs together, shared by both roles (the
+// compiler splits it evenly as soon as a kernel uses AGPRs), so all of it stays in VGPRs.
+constexpr int kWsRegKSteps = 8;
+constexpr unsigned kLdsSpinLimit = 1u << 27;  // LDS polls before giving up (seconds)
+
+// Poll bookkeeping shared by the waits: false when the launch is being abandoned.
+__device__ __forceinline__ bool keep_polling(unsigned spins, unsigned limit, unsigned* abort_flag,
+                                             unsigned* status) {
+  if ((spins & 255u) == 0 && ld_dev(abort_flag)) return false;
+  if (spins > limit) {
+    st_dev(abort_flag, 1u);
+    st_dev(status, 1u);
+    return false;
+  }
+  return true;
+}
+
+template <int NKS, bool DISC>
+__global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  __shared__ int s_flag;
+  __shared__ int s_local;
+  __shared__ int s_ready[4];  // sequence number of the product in slot w (2 m + sub + 1)
+  __shared__ int s_taken[4];  // sequence number of the last product update wave w read
+  constexpr int kPF = kKStepsUnroll;
+  static_assert(NKS % kPF == 0 && NKS >= kPF, "k-steps must be a multiple of the prefetch depth");
+  constexpr int NR = NKS < kWsRegKSteps ? NKS : kWsRegKSteps;  // J k-steps in registers
+  constexpr int NL = NKS - NR;                                 // J k-steps in LDS
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int w = wave & 3;
+  const bool product_wave = wave < 4;
+  const int g = blockIdx.x % a.groups;
+  const int mb = blockIdx.x / a.groups;
+  const int row0 = mb * 256 + w * kWaveRows;
+  const int col0 = g * kWaveCols;
+  unsigned* ctr0 = a.sync + (size_t)(2 * g) * 64;
+  unsigned* ctr1 = a.sync + (size_t)(2 * g + 1) * 64;
+  unsigned* hs = a.sync + (size_t)(2 * a.groups + g) * 64;
+  unsigned* msk = a.sync + (size_t)(3 * a.groups + g) * 64;
+  unsigned* abort_flag = a.sync + (size_t)(4 * a.groups) * 64;
+  // per generation every update wave of the group arrives once
+  const unsigned gen = 4u * (unsigned)a.nb;
+
+  // LDS: J tails [w][row tile][NL][1 KiB], then the product slots [w][row tile][lane][4 f32]
+  uint8_t* jtail = lds;
+  float* slots = reinterpret_cast<float*>(lds + (size_t)16 * NL * 1024);
+  float* slot = slots + (size_t)w * 4 * 64 * 4;
+
+  v4i jr[4][NR];
+  if (product_wave) {
+    const uint8_t* jw = static_cast<const uint8_t*>(a.jf) + (size_t)(row0 >> 4) * NKS * 1024 + lane * 16;
+    // the LDS part one row tile at a time (so that no more than one tile's fragments are
+    // in flight: registers are scarce at two waves per SIMD), then the register part,
+    // and no load of it left outstanding when the step loop begins
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+#pragma unroll
+      for (int ks = NR; ks < NKS; ++ks)
+        *reinterpret_cast<v4i*>(jtail + ((size_t)((w * 4 + rt) * NL + (ks - NR)) * 1024 + lane * 16)) =
+            *reinterpret_cast<const v4i*>(jw + (size_t)(rt * NKS + ks) * 1024);
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int ks = 0; ks < NR; ++ks) jr[rt][ks] = *reinterpret_cast<const v4i*>(jw + (size_t)(rt * NKS + ks) * 1024);
+    __builtin_amdgcn_s_waitcnt(0);
+  }
+  if (tid < 4) {
+    s_ready[tid] = 0;
+    s_taken[tid] = 0;
+  }
+
+  // Handshake: learn whether all members of this group run on one XCD.
+  if (tid == 0) {
+    const unsigned xcc = (unsigned)__builtin_amdgcn_s_getreg(kHwRegXccId) & 15u;
+    __hip_atomic_fetch_or(msk, 1u << xcc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(hs, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    unsigned spins = 0;
+    while (ld_dev(hs) < (unsigned)a.nb) {
+      ++spins;
+      if (!keep_polling(spins, kSpinLimit, abort_flag, a.status)) { ok = 0; break; }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    s_local = (__builtin_popcount(ld_dev(msk)) == 1) ? 1 : 0;
+    s_flag = ok;
+  }
+  __syncthreads();  // the last workgroup-wide barrier: the two roles run apart from here
+  const bool alive0 = s_flag != 0;
+  const int local = s_local;
+  const int steps = a.m_end - a.m_begin;
+
+  if (product_wave) {
+    // ---- product wave ----
+    // the two roles share the register file; a full wait here keeps the compiler's
+    // count of outstanding loads from carrying the update role's loads into this loop
+    __builtin_amdgcn_s_waitcnt(0);
+    const __amdgpu_buffer_rsrc_t qr = make_rsrc(a.q, 2 * a.q_buf_bytes);
+    v8i bq[kPF];
+    // the fragment's offset is uniform (a scalar register); only lane * 16 is per lane
+    const unsigned qbuf = (unsigned)__builtin_amdgcn_readfirstlane((int)a.q_buf_bytes);
+    auto load_b = [&](int sub, int buf, int ks, v8i& dst) {
+      const int soff = __builtin_amdgcn_readfirstlane((int)((unsigned)buf * qbuf +
+                                                            (unsigned)(((2 * g + sub) * NKS + ks) * 2048)));
+      const v4i lo = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, lane * 16, soff, 0));
+      const v4i hi = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, lane * 16 + 1024, soff, 0));
+      dst = cat(lo, hi);
+    };
+    auto prefetch = [&](int sub, int buf) {
+#pragma unroll
+      for (int u = 0; u < kPF; ++u) load_b(sub, buf, u, bq[u]);
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    // operand data of a column tile: every update wave of the group has arrived `target`
+    // times; then this CU's L1 holds no stale line of the operand buffers
+    auto wait_q = [&](unsigned* ctr, unsigned target) -> bool {
+      unsigned spins = 0;
+      while (ld_dev(ctr) < target) {
+        ++spins;
+        if (!keep_polling(spins, kSpinLimit, abort_flag, a.status)) return false;
+      }
+      if (!local) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      } else {
+        asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+      }
+      return true;
+    };
+    auto load_jl = [&](int ks, v4i* dst) {
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+        dst[rt] = *reinterpret_cast<const v4i*>(jtail + ((size_t)((w * 4 + rt) * NL + (ks - NR)) * 1024 + lane * 16));
+    };
+
+    // the slot flag is read half way through the K loop (it has returned by its end)
+    constexpr int kTakenAt = NKS / 2;
+    bool alive = alive0 && wait_q(ctr0, gen);
+    if (alive) prefetch(0, 0);
+    for (int s = 0; alive && s < steps; ++s) {
+      const int cur = s & 1;
+#pragma unroll
+      for (int sub = 0; sub < 2; ++sub) {
+        const int seq = 2 * s + sub + 1;
+        // the operand of the next K loop: tile 1 of this step, or tile 0 of the next
+        const bool has_next = sub == 0 || s + 1 < steps;
+        unsigned* const nctr = sub == 0 ? ctr1 : ctr0;
+        const unsigned ntarget = gen * (unsigned)(sub == 0 ? s + 1 : s + 2);
+        const int nbuf = sub == 0 ? cur : cur ^ 1;
+        int taken = 0;
+        v4f acc[4];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) acc[rt] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+        v4i jl[2][4];
+        if constexpr (NL > 0) load_jl(NR, jl[0]);
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+          __builtin_amdgcn_sched_barrier(0);
+          if constexpr (NL > 0) {
+            if (ks >= NR && ks + 1 < NKS) load_jl(ks + 1, jl[(ks + 1 - NR) & 1]);
+          }
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt) {
+            const v4i f = ks < NR ? jr[rt][ks < NR ? ks : 0] : jl[(ks - NR) & 1][rt];
+            acc[rt] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(cat(f, f), bq[ks % kPF], acc[rt], 4, 0, 0,
+                                                                       127, 0, 127);
+          }
+          asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]));
+          if (ks + kPF < NKS) load_b(sub, cur, ks + kPF, bq[ks % kPF]);
+          if (ks == kTakenAt) taken = __hip_atomic_load(&s_taken[w], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+          asm volatile("" ::: "memory");
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        // hand the product to the update wave once it has read the previous one
+        {
+          unsigned spins = 0;
+          while (taken < seq - 1 &&
+                 (taken = __hip_atomic_load(&s_taken[w], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) < seq - 1) {
+            __builtin_amdgcn_s_sleep(1);
+            if (!keep_polling(++spins, kLdsSpinLimit, abort_flag, a.status)) { alive = false; break; }
+          }
+          if (!alive) break;
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt) *reinterpret_cast<v4f*>(slot + (rt * 64 + lane) * 4) = acc[rt];
+          __hip_atomic_store(&s_ready[w], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        // operand of the next K loop
+        if (has_next) {
+          alive = wait_q(nctr, ntarget);
+          if (alive) prefetch(sub ^ 1, nbuf);
+        }
+        if (!alive) break;
+      }
+    }
+    return;
+  }
+
+  // ---- update wave ----
+  __builtin_amdgcn_s_waitcnt(0);
+  float xs[2][4][4], ys[2][4][4], ps[2][4][4];
+#pragma unroll
+  for (int sub = 0; sub < 2; ++sub)
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      const int i = row0 + rt * 16 + 4 * (lane >> 4);
+      const int r = col0 + sub * 16 + (lane & 15);
+      const size_t o = (size_t)r * a.np + i;
+      const v4f vx = *reinterpret_cast<const v4f*>(a.x + o);
+      const v4f vy = *reinterpret_cast<const v4f*>(a.y + o);
+      const v4f vp = *reinterpret_cast<const v4f*>(a.p + o);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) { xs[sub][rt][v] = vx[v]; ys[sub][rt][v] = vy[v]; ps[sub][rt][v] = vp[v]; }
+    }
+  // count this wave in at `ctr` once its operand stores are acknowledged (then in L2)
+  auto arrive = [&](unsigned* ctr) {
+    __builtin_amdgcn_s_waitcnt(0);
+    if (lane == 0) {
+      if (!local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  };
+  const float A = a.A, dt = a.dt, cdt = a.cdt;
+  // eqs. (7), (3), (4), (5) for column tile `sub`, in two parts: `before` needs only the
+  // state and runs while the product wave computes the tile's product; `after` adds the
+  // product (acc), applies the wall and writes the operand.  t carries y + dy between them.
+  float t[16];
+  auto before = [&](int sub, float rm) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) { const float x = xs[sub][e >> 2][e & 3]; t[e] = x * x; }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t[e] = A * t[e];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t[e] = 1.0f - t[e];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t[e] = t[e] * ps[sub][e >> 2][e & 3];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t[e] = t[e] * rm;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) ps[sub][e >> 2][e & 3] = ps[sub][e >> 2][e & 3] - t[e];  // p(t_{m+1})
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t[e] = ps[sub][e >> 2][e & 3] * xs[sub][e >> 2][e & 3];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t[e] = t[e] * dt;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t[e] = ys[sub][e >> 2][e & 3] - t[e];            // y + dy
+  };
+  auto after = [&](int sub, const v4f* acc, uint8_t* qnext) {
+    float u[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) u[e] = cdt * acc[e >> 2][e & 3];                 // Dy
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t[e] = t[e] + u[e];                              // eq. (3)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) u[e] = t[e] * dt;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) u[e] = xs[sub][e >> 2][e & 3] + u[e];            // eq. (4)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {                                                // eq. (5)
+      ys[sub][e >> 2][e & 3] = __builtin_fabsf(u[e]) > 1.0f ? 0.0f : t[e];
+      xs[sub][e >> 2][e & 3] = __builtin_amdgcn_fmed3f(u[e], -1.0f, 1.0f);
+    }
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+      store_operand<kFormFP8, DISC>(qnext, a.q_buf_bytes, NKS, row0 + rt * 16, col0 + sub * 16, lane,
+                                    xs[sub][rt]);
+  };
+
+  bool alive = alive0;
+  if (alive) {
+#pragma unroll
+    for (int sub = 0; sub < 2; ++sub)
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+        store_operand<kFormFP8, DISC>(a.q, a.q_buf_bytes, NKS, row0 + rt * 16, col0 + sub * 16, lane,
+                                      xs[sub][rt]);
+    arrive(ctr0);
+    arrive(ctr1);
+  }
+  for (int s = 0; alive && s < steps; ++s) {
+    const int m = a.m_begin + s;
+    uint8_t* qnext = a.q + (size_t)((s + 1) & 1) * a.q_buf_bytes;
+    const float rm = a.rtab[m];
+#pragma unroll
+    for (int sub = 0; sub < 2; ++sub) {
+      const int seq = 2 * s + sub + 1;
+      before(sub, rm);
+      unsigned spins = 0;
+      while (__hip_atomic_load(&s_ready[w], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < seq) {
+        if (!keep_polling(++spins, kLdsSpinLimit, abort_flag, a.status)) { alive = false; break; }
+      }
+      if (!alive) break;
+      v4f acc[4];
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) acc[rt] = *reinterpret_cast<const v4f*>(slot + (rt * 64 + lane) * 4);
+      __hip_atomic_store(&s_taken[w], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      after(sub, acc, qnext);
+      arrive(sub == 0 ? ctr0 : ctr1);
+    }
+  }
+
+#pragma unroll
+  for (int sub = 0; sub < 2; ++sub)
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      const int i = row0 + rt * 16 + 4 * (lane >> 4);
+      const int r = col0 + sub * 16 + (lane & 15);
+      const size_t o = (size_t)r * a.np + i;
+      *reinterpret_cast<v4f*>(a.x + o) = v4f{xs[sub][rt][0], xs[sub][rt][1], xs[sub][rt][2], xs[sub][rt][3]};
+      *reinterpret_cast<v4f*>(a.y + o) = v4f{ys[sub][rt][0], ys[sub][rt][1], ys[sub][rt][2], ys[sub][rt][3]};
+      *reinterpret_cast<v4f*>(a.p + o) = v4f{ps[sub][rt][0], ps[sub][rt][1], ps[sub][rt][2], ps[sub][rt][3]};
+    }
+}
+
+}  // namespace
+
+const void* steps_kernel_ws(int nks, bool discrete) {
+  if (discrete) {
+    switch (nks) {
+      case 4: return reinterpret_cast<const void*>(&k_steps_ws<4, true>);
+      case 8: return reinterpret_cast<const void*>(&k_steps_ws<8, true>);
+      case 12: return reinterpret_cast<const void*>(&k_steps_ws<12, true>);
+      case 16: return reinterpret_cast<const void*>(&k_steps_ws<16, true>);
+      default: return nullptr;
+    }
+  }
+  switch (nks) {
+    case 4: return reinterpret_cast<const void*>(&k_steps_ws<4, false>);
+    case 8: return reinterpret_cast<const void*>(&k_steps_ws<8, false>);
+    case 12: return reinterpret_cast<const void*>(&k_steps_ws<12, false>);
+    case 16: return reinterpret_cast<const void*>(&k_steps_ws<16, false>);
+    default: return nullptr;
+  }
+}
+
+size_t steps_ws_lds_bytes(int np) {
+  const int nks = np / kKS;
+  const int nl = nks > kWsRegKSteps ? nks - kWsRegKSteps : 0;
+  return (size_t)16 * nl * 1024 + (size_t)4 * 4 * 64 * 16;
+}
+
+}  // namespace gsb

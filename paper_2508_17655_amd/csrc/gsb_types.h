@@ -27,10 +27,15 @@ enum Form { kFormFP32 = 0, kFormBF16X2 = 1, kFormFP8 = 2, kFormFIX16 = 3 };
 //   kKindGeneric : J fragments from L2 (any form; FP4 J for the FP8 product), 64 spins x
 //               128 replicas per workgroup (the batched kernel also runs 128 x 64 and
 //               256 x 32 tiles).
-enum Kind { kKindGeneric = 0, kKindRegJ = 2 };
+//   kKindWaveSpec : FP8 product, np <= 2048, the kKindRegJ tile with two waves per SIMD:
+//               one computes the product (J in registers and LDS), the other the update.
+enum Kind { kKindGeneric = 0, kKindRegJ = 2, kKindWaveSpec = 3 };
 
-__host__ __device__ constexpr int tile_rows_kind(int kind) { return kind == kKindRegJ ? 256 : 64; }
+__host__ __device__ constexpr int tile_rows_kind(int kind) {
+  return (kind == kKindRegJ || kind == kKindWaveSpec) ? 256 : 64;
+}
 __host__ __device__ constexpr int tile_cols_kind(int kind) { return 8192 / tile_rows_kind(kind); }
+__host__ __device__ constexpr int threads_kind(int kind) { return kind == kKindWaveSpec ? 2 * kThreads : kThreads; }
 
 // Bytes of one operand plane per (16-replica block, k-step) and of one J block per
 // (16-row tile, k-step), in the fragment-major layouts.  (The register-resident FP8 path

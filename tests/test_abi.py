@@ -67,6 +67,11 @@ def test_options_and_errors_without_device():
         assert _status(gsb.gsb_init, ctx, 0, 0, 0.0, 1.0, 4, 0, 1) == gsb.GSB_EINVAL
         gsb.gsb_set(ctx, gsb.GSB_OPT_C, 0.25)
         assert gsb.gsb_get(ctx, gsb.GSB_OPT_C) == 0.25
+        assert gsb.gsb_get(ctx, gsb.GSB_OPT_STEP_KERNEL) == 0
+        for bad in (-1, 3, 1.5):
+            assert _status(gsb.gsb_set, ctx, gsb.GSB_OPT_STEP_KERNEL, bad) == gsb.GSB_EINVAL
+        gsb.gsb_set(ctx, gsb.GSB_OPT_STEP_KERNEL, 2)
+        assert gsb.gsb_get(ctx, gsb.GSB_OPT_STEP_KERNEL) == 2
     finally:
         gsb.gsb_destroy(ctx)
     ctx = gsb.gsb_create(instances.dense_gaussian(10, 2))

@@ -184,6 +184,34 @@ def test_fp8_generic_kernel_bitexact(orc, variant):
     check_exact(E, orc.energy(J, orc.spins(x)), "energies")
 
 
+@pytest.mark.parametrize("n", [333, 1000, 1500, 2000])
+def test_both_fp8_step_kernels_bitexact(orc, n):
+    # The two FP8 step kernels for n_p <= 2048 (1: product and update in one wave per SIMD;
+    # 2: in two waves per SIMD, J partly in LDS from n_p = 1536 on) give the same bits,
+    # and the oracle's.
+    R, M, A, seed = 96, 120, 0.2, 5
+    say(f"case step kernels n={n} R={R} M={M}")
+    J = instances.dense_pm1(n, 21)
+    c = instances.paper_c(n)
+    for variant in ("gbsb", "gdsb"):
+        got = {}
+        for k in (1, 2):
+            g = gsb.GSB(J, precision="fp8", c=c, step_kernel=k)
+            assert gsb.gsb_get(g.ctx, gsb.GSB_OPT_STEP_KERNEL) == k
+            g.run(variant, A=A, dt=1.25, replicas=R, steps=M, seed=seed)
+            got[k] = g.state()[:3] + (g.energy(),)
+            g.close()
+        for a, b, what in zip(got[1], got[2], ("x", "y", "p", "E")):
+            check_exact(a, b, f"kernel 1 vs 2, {variant} {what}")
+        sample = np.array([0, 47, 95])
+        x0, y0, p0 = oracle_start(orc, n, R, seed, orc.INIT_X)
+        form = orc.FORM_E4M3 if variant == "gbsb" else orc.FORM_EXACT
+        xo, yo, po = orc.run(J, orc.VARIANTS[variant], A=A, dt=1.25, c=c, steps=M, x=x0[sample], y=y0[sample],
+                             p=p0[sample], form=form, mode="fp32")
+        x, y, p, _ = got[2]
+        check_exact(x[sample], xo, "x"); check_exact(y[sample], yo, "y"); check_exact(p[sample], po, "p")
+
+
 @pytest.mark.parametrize("precision,variant,form", [("fp8", "gbsb", "e4m3"), ("fix16", "gbsb", "fix16"),
                                                      ("bf16x2", "gdsb", "exact"), ("fp32", "dsb", "exact")])
 def test_more_replicas_than_one_launch_holds(orc, precision, variant, form):
