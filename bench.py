@@ -69,8 +69,9 @@ def _finite(v: float):
     return v if math.isfinite(v) else None
 
 
-# sources that determine the register-resident step kernel's machine code
-RJ_SOURCES = ("gsb_steps_rj.hip", "gsb_device.h", "gsb_types.h")
+# sources that determine the headline step kernel's machine code (the wave-specialised
+# FP8 kernel, the automatic choice at n_p <= 2048)
+RJ_SOURCES = ("gsb_steps_ws.hip", "gsb_device.h", "gsb_types.h")
 
 
 def kernel_source_hash() -> str:
@@ -446,9 +447,9 @@ def main():
         "fp32_form": fp32_form,
         "fix16_form": fix16_form,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP8_PEAK / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved * 1e12 / FP8_PEAK, "traffic": load_traffic("k_steps_rj_fp8_n2000_r1024_counters.json"),
-                     "mfma_busy_frac_counters": load_mfma_busy("k_steps_rj_fp8_n2000_r1024_mfma_counters.json"),
-                     "kernel": "k_steps_rj<16> (FP8 product, J resident in registers)", "kernel_ms_per_launch": k_ms,
+                     "frac": achieved * 1e12 / FP8_PEAK, "traffic": load_traffic("k_steps_ws_fp8_n2000_r1024_counters.json"),
+                     "mfma_busy_frac_counters": load_mfma_busy("k_steps_ws_fp8_n2000_r1024_mfma_counters.json"),
+                     "kernel": "k_steps_ws<16> (FP8 product, J resident in VGPRs and LDS; product and update in separate waves)", "kernel_ms_per_launch": k_ms,
                      "flop_per_launch": flop},
     }
 

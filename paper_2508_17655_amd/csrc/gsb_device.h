@@ -17,12 +17,12 @@ typedef unsigned v2u __attribute__((ext_vector_type(2)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
-// Cache policies of operand loads.  Device scope skips L1, so the operand, which no two
-// waves of a workgroup share, does not evict the J lines they do share.  Plain loads may
-// hit L1; every barrier that publishes an operand buffer invalidates the reader CU's L1
-// (group_sync), so no stale line survives either way.
+// Cache policies of loads.  Operand (Q) loads use device scope, which skips L1: the
+// operand buffers are rewritten every step by other CUs, and a workgroup-scope L1
+// invalidate does not reliably drop such lines on gfx950 (measured: stale operands when
+// the buffers fit in L1), while an agent-scope invalidate costs microseconds.  Plain
+// loads (J, read-only for a launch) may hit L1.
 constexpr int kPolicySc1 = 16;
-constexpr int kPolicyPlain = 0;
 constexpr unsigned kSpinLimit = 1u << 22;  // polls before a barrier gives up (seconds)
 constexpr int kHwRegXccId = 20 | (0 << 6) | ((4 - 1) << 11);  // hwreg(HW_REG_XCC_ID, 0, 4)
 
@@ -44,8 +44,8 @@ __device__ __forceinline__ void st_dev(unsigned* p, unsigned v) {
 // Barrier over the `nb` workgroups that share a replica group.  Every wave first waits
 // until its own stores are acknowledged (they are then in L2), then one thread counts
 // the workgroup in and polls the counter with device-scope loads.  When all members sit
-// on one XCD (`local`) they share that XCD's L2: invalidating this CU's L1 is all the
-// cache maintenance the next operand loads need; otherwise the agent-scope
+// on one XCD (`local`) they share that XCD's L2, which the operand loads read directly
+// (they bypass L1), so no cache maintenance is needed; otherwise the agent-scope
 // release/acquire fences write back and invalidate the caches between XCDs.
 __device__ __forceinline__ bool group_sync(unsigned* ctr, unsigned target, int local,
                                            unsigned* abort_flag, unsigned* status, int* s_flag) {
@@ -62,11 +62,7 @@ __device__ __forceinline__ bool group_sync(unsigned* ctr, unsigned target, int l
       if ((spins & 63u) == 0 && ld_dev(abort_flag)) { ok = 0; break; }
       if (spins > kSpinLimit) { st_dev(abort_flag, 1u); st_dev(status, 1u); ok = 0; break; }
     }
-    if (!local) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    } else {
-      asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
-    }
+    if (!local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *s_flag = ok;
   }
   __syncthreads();

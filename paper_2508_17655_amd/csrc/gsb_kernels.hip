@@ -82,9 +82,8 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
   static_assert(BM == 64 || BM == 128 || BM == 256, "tile rows");
   constexpr int BN = 8192 / BM;
   constexpr int WCOLS = BN / kWaveCols;  // waves across the replica columns
-  // with J in L1 (read by the waves of a workgroup) the operand skips L1; with J in LDS
-  // it may use L1
-  constexpr int kQPolicy = LJ ? kPolicyPlain : kPolicySc1;
+  // operand loads bypass L1 (see kPolicySc1)
+  constexpr int kQPolicy = kPolicySc1;
 
   // the wave index is uniform within a wave; readfirstlane tells the compiler so
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);

@@ -21,8 +21,7 @@ constexpr int kAccKSteps = 14;  // k-steps of J held in AGPRs (the rest in VGPRs
 // 0 and +-1), in registers for the whole launch: 4 row tiles x NKS fragments of 16 bytes
 // per lane, k-steps [0, kAccKSteps) in accumulation registers (AGPRs, which the MFMA reads
 // directly as its A operand) and the rest in VGPRs; at np = 2048 that is 224 AGPRs of J
-// beside the 16 of the accumulators.  The four waves read the same Q fragments, which
-// come through L1.
+// beside the 16 of the accumulators.  The four waves read the same Q fragments, from L2.
 //
 // The 32 replica columns form two independent sub-groups of 16 (column tiles 0 and 1),
 // each with its own barrier counter, processed half a step apart:
@@ -120,8 +119,9 @@ __global__ void __launch_bounds__(kThreads, 1) __attribute__((amdgpu_waves_per_e
       __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   };
-  // wait: every member has arrived `target` times on `ctr`; then this CU's L1 holds no
-  // stale copy of the operand buffer (it is invalidated), so plain loads see the data.
+  // wait: every member has arrived `target` times on `ctr` (across XCDs, behind an
+  // agent-scope acquire fence).  The operand loads bypass L1, so no L1 line can be stale
+  // (a workgroup-scope invalidate does not reliably drop lines other CUs have rewritten).
   // `seen` is a count read earlier (mid K loop); when it already reaches the target the
   // poll round trip is skipped.
   auto wait = [&](unsigned* ctr, unsigned target, unsigned seen) -> bool {
@@ -135,11 +135,7 @@ __global__ void __launch_bounds__(kThreads, 1) __attribute__((amdgpu_waves_per_e
         if ((spins & 63u) == 0 && ld_dev(abort_flag)) { ok = 0; break; }
         if (spins > kSpinLimit) { st_dev(abort_flag, 1u); st_dev(a.status, 1u); ok = 0; break; }
       }
-      if (!local) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      } else {
-        asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
-      }
+      if (!local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       s_flag = ok;
     }
     __syncthreads();
@@ -152,8 +148,8 @@ __global__ void __launch_bounds__(kThreads, 1) __attribute__((amdgpu_waves_per_e
   auto load_b = [&](int sub, int buf, int ks, v8i& dst) {
     const unsigned base = (unsigned)((size_t)buf * a.q_buf_bytes) +
                           (unsigned)(((2 * g + sub) * NKS + ks) * 2048 + lane * 16);
-    const v4i lo = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, 0));
-    const v4i hi = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base + 1024, 0, 0));
+    const v4i lo = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base, 0, kPolicySc1));
+    const v4i hi = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, base + 1024, 0, kPolicySc1));
     dst = cat(lo, hi);
   };
   auto prefetch = [&](int sub, int buf) {

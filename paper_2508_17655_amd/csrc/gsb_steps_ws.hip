@@ -47,6 +47,8 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
   __shared__ int s_local;
   __shared__ int s_ready[4];  // sequence number of the product in slot w (2 m + sub + 1)
   __shared__ int s_taken[4];  // sequence number of the last product update wave w read
+  __shared__ int s_pw_arrived;  // product waves that have handed over their product
+  __shared__ int s_pw_go;       // product waves may load the operand of this sequence number
   constexpr int kPF = kKStepsUnroll;
   static_assert(NKS % kPF == 0 && NKS >= kPF, "k-steps must be a multiple of the prefetch depth");
   constexpr int NR = NKS < kWsRegKSteps ? NKS : kWsRegKSteps;  // J k-steps in registers
@@ -98,6 +100,7 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
     s_ready[tid] = 0;
     s_taken[tid] = 0;
   }
+  if (tid == 0) { s_pw_arrived = 0; s_pw_go = -1; }
 
   // Handshake: learn whether all members of this group run on one XCD.
   if (tid == 0) {
@@ -127,13 +130,17 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
     __builtin_amdgcn_s_waitcnt(0);
     const __amdgpu_buffer_rsrc_t qr = make_rsrc(a.q, 2 * a.q_buf_bytes);
     v8i bq[kPF];
-    // the fragment's offset is uniform (a scalar register); only lane * 16 is per lane
+    // Operand loads bypass L1 (device scope) and need no cache maintenance: a workgroup-
+    // scope invalidate does not reliably drop L1 lines that other CUs have rewritten (a
+    // race that shows when the operand fits in L1), and an agent-scope one costs
+    // microseconds.  The fragment's offset is uniform (a scalar register); only lane * 16
+    // is per lane.
     const unsigned qbuf = (unsigned)__builtin_amdgcn_readfirstlane((int)a.q_buf_bytes);
     auto load_b = [&](int sub, int buf, int ks, v8i& dst) {
       const int soff = __builtin_amdgcn_readfirstlane((int)((unsigned)buf * qbuf +
                                                             (unsigned)(((2 * g + sub) * NKS + ks) * 2048)));
-      const v4i lo = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, lane * 16, soff, 0));
-      const v4i hi = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, lane * 16 + 1024, soff, 0));
+      const v4i lo = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, lane * 16, soff, kPolicySc1));
+      const v4i hi = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(qr, lane * 16 + 1024, soff, kPolicySc1));
       dst = cat(lo, hi);
     };
     auto prefetch = [&](int sub, int buf) {
@@ -143,18 +150,14 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
       __builtin_amdgcn_sched_barrier(0);
     };
     // operand data of a column tile: every update wave of the group has arrived `target`
-    // times; then this CU's L1 holds no stale line of the operand buffers
+    // times (across XCDs, behind an agent-scope acquire fence)
     auto wait_q = [&](unsigned* ctr, unsigned target) -> bool {
       unsigned spins = 0;
       while (ld_dev(ctr) < target) {
         ++spins;
         if (!keep_polling(spins, kSpinLimit, abort_flag, a.status)) return false;
       }
-      if (!local) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      } else {
-        asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
-      }
+      if (!local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       return true;
     };
     auto load_jl = [&](int ks, v4i* dst) {
@@ -165,7 +168,29 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
 
     // the slot flag is read half way through the K loop (it has returned by its end)
     constexpr int kTakenAt = NKS / 2;
-    bool alive = alive0 && wait_q(ctr0, gen);
+    // The four product waves meet before each operand switch: wave 0 polls the group
+    // counter once all four have handed over their product, then all load (one poller per
+    // workgroup instead of four, and the four load the same fragments together).
+    auto pw_sync = [&](int seqv, unsigned* ctr, unsigned target) -> bool {
+      bool ok = true;
+      if (w == 0) {
+        unsigned spins = 0;
+        while (__hip_atomic_load(&s_pw_arrived, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < 4 * seqv) {
+          if (!keep_polling(++spins, kLdsSpinLimit, abort_flag, a.status)) { ok = false; break; }
+        }
+        if (ok) ok = wait_q(ctr, target);
+        __hip_atomic_store(&s_pw_go, ok ? seqv : -1000000, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        return ok;
+      }
+      unsigned spins = 0;
+      int gv;
+      while ((gv = __hip_atomic_load(&s_pw_go, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) < seqv) {
+        if (gv == -1000000) return false;
+        if (!keep_polling(++spins, kLdsSpinLimit, abort_flag, a.status)) return false;
+      }
+      return true;
+    };
+    bool alive = alive0 && pw_sync(0, ctr0, gen);
     if (alive) prefetch(0, 0);
     for (int s = 0; alive && s < steps; ++s) {
       const int cur = s & 1;
@@ -215,8 +240,9 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
           __hip_atomic_store(&s_ready[w], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         // operand of the next K loop
+        __hip_atomic_fetch_add(&s_pw_arrived, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (has_next) {
-          alive = wait_q(nctr, ntarget);
+          alive = pw_sync(seq, nctr, ntarget);
           if (alive) prefetch(sub ^ 1, nbuf);
         }
         if (!alive) break;
