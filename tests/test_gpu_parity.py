@@ -189,7 +189,7 @@ def test_both_fp8_step_kernels_bitexact(orc, n):
     # The two FP8 step kernels for n_p <= 2048 (1: product and update in one wave per SIMD;
     # 2: in two waves per SIMD, J partly in LDS from n_p = 1536 on) give the same bits,
     # and the oracle's.
-    R, M, A, seed = 96, 120, 0.2, 5
+    R, M, A, seed = 200, 120, 0.2, 5  # 8 replica groups: each on one XCD
     say(f"case step kernels n={n} R={R} M={M}")
     J = instances.dense_pm1(n, 21)
     c = instances.paper_c(n)
@@ -203,13 +203,32 @@ def test_both_fp8_step_kernels_bitexact(orc, n):
             g.close()
         for a, b, what in zip(got[1], got[2], ("x", "y", "p", "E")):
             check_exact(a, b, f"kernel 1 vs 2, {variant} {what}")
-        sample = np.array([0, 47, 95])
+        sample = np.array([0, 47, 95, 150, 199])
         x0, y0, p0 = oracle_start(orc, n, R, seed, orc.INIT_X)
         form = orc.FORM_E4M3 if variant == "gbsb" else orc.FORM_EXACT
         xo, yo, po = orc.run(J, orc.VARIANTS[variant], A=A, dt=1.25, c=c, steps=M, x=x0[sample], y=y0[sample],
                              p=p0[sample], form=form, mode="fp32")
         x, y, p, _ = got[2]
         check_exact(x[sample], xo, "x"); check_exact(y[sample], yo, "y"); check_exact(p[sample], po, "p")
+
+
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_operand_small_enough_for_l1(orc, kernel):
+    # Regression: with XCD-local replica groups and an operand that fits in L1 (n_p = 512),
+    # a workgroup-scope L1 invalidate let stale operand lines through now and then (whole
+    # 16-replica tiles diverged, differently from run to run).  Every replica, 300 steps.
+    n, R, M, seed = 333, 200, 300, 5
+    say(f"case operand in L1 kernel={kernel} n={n} R={R} M={M}")
+    J = instances.dense_pm1(n, 2)
+    c = instances.paper_c(n)
+    x0, y0, p0 = oracle_start(orc, n, R, seed, orc.INIT_X)
+    xo, yo, po = orc.run(J, orc.DSB, A=0.3, dt=1.25, c=c, steps=M, x=x0, y=y0, p=p0, mode="fp32")
+    for rep in range(3):
+        g = gsb.GSB(J, precision="fp8", c=c, step_kernel=kernel)
+        g.run("dsb", A=0.3, dt=1.25, replicas=R, steps=M, seed=seed)
+        x, y, p, _ = g.state()
+        g.close()
+        check_exact(x, xo, f"x (run {rep})"); check_exact(y, yo, f"y (run {rep})"); check_exact(p, po, f"p (run {rep})")
 
 
 @pytest.mark.parametrize("precision,variant,form", [("fp8", "gbsb", "e4m3"), ("fix16", "gbsb", "fix16"),
