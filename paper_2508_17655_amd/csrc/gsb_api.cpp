@@ -186,6 +186,7 @@ struct gsb_ctx {
   double A = 0, dt = 0;
   uint64_t seed = 0;
   int chunk_rp = 0;
+  int max_wg = 0;  // co-resident workgroups of the step kernel
   int kind = 0;
   std::vector<float> rtab_host;
   // device memory
@@ -226,6 +227,7 @@ struct Layout {
   size_t acol = 0, lg = 0, ext = 0;  // tangent mode only
   size_t q_buf_bytes;
   int chunk_rp;  // columns per launch
+  int max_wg;    // co-resident workgroups of the step kernel
 };
 
 // Workspace of a run of R replicas over M steps.  Tangent mode (gsb_lle): binary32 form,
@@ -273,6 +275,7 @@ gsb_status plan(gsb_ctx* c, int R, int M, Layout* L, int* kind_out, bool tangent
   }
   L->total = off;
   L->chunk_rp = chunk_rp;
+  L->max_wg = max_wg;
   *kind_out = kind;
   return GSB_OK;
 }
@@ -561,6 +564,7 @@ gsb_status carve_and_prepare(gsb_ctx* c, const Layout& L, int kind, int form, in
   c->best_e = reinterpret_cast<double*>(b + L.best + 8);
   c->spins = reinterpret_cast<int8_t*>(b + L.spins);
   c->chunk_rp = L.chunk_rp;
+  c->max_wg = L.max_wg;
   c->kind = kind;
   if (!c->j32_ready) {
     HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(c->j32), (size_t)c->np * c->np, 0u, c->stream), "clear J");
@@ -618,6 +622,11 @@ gsb_status launch_chunks(gsb_ctx* c, int form, int cols, bool discrete, float A,
     a.status = c->status;
     a.tape = tape ? tape + (size_t)r0 * c->np : nullptr;
     a.tape_arr = (size_t)cols * c->np;
+    // pad the grid to whole XCD rounds of groups when that still fits (kernel launches only)
+    if (!adjoint) {
+      const int gp = (a.groups + 7) / 8 * 8;
+      a.gpad = (c->max_wg > 0 && gp * a.nb <= c->max_wg) ? gp : a.groups;
+    }
     HIP_TRY(launch_fill_u32(c->sync, sync_words(a.groups), 0u, c->stream), "clear sync");
     if (adjoint) {
       HIP_TRY(launch_adjoint(a, c->stream), "adjoint kernel launch");

@@ -559,7 +559,9 @@ __global__ void __launch_bounds__(kThreads, 1) k_steps(StepArgs a) {
   __shared__ int s_local;
   // LJ: the workgroup's 64 rows of J in LDS, 64 np bytes (int8, FIX16) or 32 np (FP4, FP8)
   extern __shared__ __attribute__((aligned(16))) uint8_t lds_j[];
-  steps_tile<FORM, DISC, TANG, 64, LJ>(a, (int)(blockIdx.x % a.groups), (int)(blockIdx.x / a.groups), s_flag,
+  const int gg = grid_groups(a);
+  if ((int)(blockIdx.x % gg) >= a.groups) return;  // a padding workgroup (see StepArgs::gpad)
+  steps_tile<FORM, DISC, TANG, 64, LJ>(a, (int)(blockIdx.x % gg), (int)(blockIdx.x / gg), s_flag,
                                        s_local, LJ ? lds_j : nullptr,
                                        LJ ? (FORM == kFormFIX16 ? 64 : 32) * a.np : 0);
 }
@@ -1415,7 +1417,7 @@ hipError_t launch_steps(int form, int kind, const StepArgs& a, hipStream_t strea
   }
   StepArgs copy = a;
   void* args[] = {&copy};
-  return hipLaunchCooperativeKernel(k, dim3(a.groups * a.nb), dim3(threads_kind(kind)), args, (unsigned)lds,
+  return hipLaunchCooperativeKernel(k, dim3(grid_groups(a) * a.nb), dim3(threads_kind(kind)), args, (unsigned)lds,
                                     stream);
 }
 

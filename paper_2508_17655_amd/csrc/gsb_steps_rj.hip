@@ -42,8 +42,9 @@ __global__ void __launch_bounds__(kThreads, 1) __attribute__((amdgpu_waves_per_e
 
   // the wave index is uniform within a wave; readfirstlane tells the compiler so
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int g = blockIdx.x % a.groups;
-  const int mb = blockIdx.x / a.groups;
+  const int g = blockIdx.x % grid_groups(a);
+  const int mb = blockIdx.x / grid_groups(a);
+  if (g >= a.groups) return;  // a padding workgroup (see StepArgs::gpad)
   const int row0 = mb * 256 + wave * kWaveRows;
   const int col0 = g * kWaveCols;
   unsigned* ctr0 = a.sync + (size_t)(2 * g) * 64;

@@ -58,8 +58,9 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int w = wave & 3;
   const bool product_wave = wave < 4;
-  const int g = blockIdx.x % a.groups;
-  const int mb = blockIdx.x / a.groups;
+  const int g = blockIdx.x % grid_groups(a);
+  const int mb = blockIdx.x / grid_groups(a);
+  if (g >= a.groups) return;  // a padding workgroup (see StepArgs::gpad)
   const int row0 = mb * 256 + w * kWaveRows;
   const int col0 = g * kWaveCols;
   unsigned* ctr0 = a.sync + (size_t)(2 * g) * 64;

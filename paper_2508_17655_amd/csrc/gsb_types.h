@@ -67,7 +67,13 @@ struct StepArgs {
   unsigned* status;       // set nonzero on a device-side timeout
   float* tape = nullptr;  // binary32 form: per-step input states (reverse pass), or nullptr
   size_t tape_arr = 0;    // floats between the x, y, p planes of one tape entry
+  // Workgroups per row block in the grid: 0 (= groups), or groups rounded up to a
+  // multiple of 8 so that workgroup b, which runs on XCD b mod 8, belongs to a group whose
+  // workgroups all share that XCD; workgroups of the padding groups exit at once.
+  int gpad = 0;
 };
+
+__host__ __device__ inline int grid_groups(const StepArgs& a) { return a.gpad > 0 ? a.gpad : a.groups; }
 
 inline size_t sync_words(int groups) { return (size_t)(4 * groups + 1) * 64; }
 
