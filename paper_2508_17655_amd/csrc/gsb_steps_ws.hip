@@ -12,8 +12,9 @@
 //     (4), (5) in binary32 (one rounding per operator), writes the next operand and
 //     counts itself in at that column tile's group counter.
 // The matrix cores and the vector ALU of a SIMD execute instructions of different waves
-// at the same time, so the update of one column tile runs under the K loop of the other,
-// and no product wave waits at a barrier other than for its operand data.
+// at the same time, so the update of one column tile runs under the K loop of the other.
+// The product waves meet (in LDS) only before each switch of operand, where one of them
+// polls the group counter for all four.
 #include "gsb_device.h"
 
 #pragma clang fp contract(off)
@@ -27,6 +28,7 @@ constexpr int kWsThreads = 512;
 // compiler splits it evenly as soon as a kernel uses AGPRs), so all of it stays in VGPRs.
 constexpr int kWsRegKSteps = 8;
 constexpr unsigned kLdsSpinLimit = 1u << 27;  // LDS polls before giving up (seconds)
+constexpr int kPwAbandoned = -1000000;        // s_pw_go when the poller gave up
 
 // Poll bookkeeping shared by the waits: false when the launch is being abandoned.
 __device__ __forceinline__ bool keep_polling(unsigned spins, unsigned limit, unsigned* abort_flag,
@@ -180,13 +182,13 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
           if (!keep_polling(++spins, kLdsSpinLimit, abort_flag, a.status)) { ok = false; break; }
         }
         if (ok) ok = wait_q(ctr, target);
-        __hip_atomic_store(&s_pw_go, ok ? seqv : -1000000, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_store(&s_pw_go, ok ? seqv : kPwAbandoned, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         return ok;
       }
       unsigned spins = 0;
       int gv;
       while ((gv = __hip_atomic_load(&s_pw_go, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) < seqv) {
-        if (gv == -1000000) return false;
+        if (gv == kPwAbandoned) return false;
         if (!keep_polling(++spins, kLdsSpinLimit, abort_flag, a.status)) return false;
       }
       return true;
