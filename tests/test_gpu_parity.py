@@ -212,6 +212,29 @@ def test_both_fp8_step_kernels_bitexact(orc, n):
         check_exact(x[sample], xo, "x"); check_exact(y[sample], yo, "y"); check_exact(p[sample], po, "p")
 
 
+@pytest.mark.parametrize("precision,kernel,variant,form", [("fp8", 1, "gbsb", "e4m3"), ("fp8", 2, "gbsb", "e4m3"),
+                                                            ("fix16", 0, "gbsb", "fix16"), ("fp32", 0, "gdsb", "exact")])
+def test_small_launch_on_padded_grid(orc, precision, kernel, variant, form):
+    # 40 replicas are one or a few replica groups; the grid is padded to whole rounds of 8
+    # groups (padding workgroups exit at once) so that each group shares one XCD.
+    n, R, M, A, seed = 700, 40, 150, 0.2, 8
+    say(f"case padded grid precision={precision} kernel={kernel} n={n} R={R} M={M}")
+    J = instances.dense_pm1(n, 6)
+    c = instances.paper_c(n)
+    g = gsb.GSB(J, precision=precision, c=c, step_kernel=kernel)
+    g.run(variant, A=A, dt=1.25, replicas=R, steps=M, seed=seed)
+    x, y, p, _ = g.state()
+    E = g.energy()
+    g.close()
+    sample = np.array([0, 17, 39])
+    x0, y0, p0 = oracle_start(orc, n, R, seed, orc.INIT_X)
+    f = {"e4m3": orc.FORM_E4M3, "fix16": orc.FORM_FIX16, "exact": orc.FORM_EXACT}[form]
+    xo, yo, po = orc.run(J, orc.VARIANTS[variant], A=A, dt=1.25, c=c, steps=M, x=x0[sample], y=y0[sample],
+                         p=p0[sample], form=f, mode="fp32")
+    check_exact(x[sample], xo, "x"); check_exact(y[sample], yo, "y"); check_exact(p[sample], po, "p")
+    check_exact(E, orc.energy(J, orc.spins(x)), "energies")
+
+
 @pytest.mark.parametrize("kernel", [1, 2])
 def test_operand_small_enough_for_l1(orc, kernel):
     # Regression: with XCD-local replica groups and an operand that fits in L1 (n_p = 512),
