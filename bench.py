@@ -333,6 +333,8 @@ def main():
     ap.add_argument("--no-dt", action="store_true", help="skip the time-step study")
     ap.add_argument("--no-precision", action="store_true", help="skip the 4096-replica precision workload")
     ap.add_argument("--profile", action="store_true", help="few untimed runs only (for rocprofv3)")
+    ap.add_argument("--profile-small", action="store_true",
+                    help="untimed launches of 16 and 128 replicas only (for rocprofv3 cache counters)")
     ap.add_argument("--profile-batch", action="store_true",
                     help="the batched workload, autotuned, then two untimed runs (for rocprofv3)")
     args = ap.parse_args()
@@ -360,6 +362,20 @@ def main():
     c = instances.paper_c(N)
     g8 = gsb.GSB(J, precision="fp8", c=c)
 
+    if args.profile_small:
+        # small launches: three of 16 replicas, then three of 128, then the streaming
+        # kernel of known size that scales the byte counters
+        for r_small in (16, 128):
+            for s in range(3):
+                g8.run("gbsb", A=A_HEAD, dt=DT, replicas=r_small, steps=M, seed=300 + s)
+                g8.best()
+        a = torch.zeros(64 * 2**20, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.add(a, 1, out=b)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_runs": 6, "replicas": [16, 128], "copy_bytes": a.numel() * 4}))
+        return
     if args.profile:
         for s in range(3):
             g8.run("gbsb", A=A_HEAD, dt=DT, replicas=R, steps=M, seed=100 + s)
