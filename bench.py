@@ -82,9 +82,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(name: str):
-    """HBM bytes per launch of the step kernel from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
+def load_counters(name: str):
+    """The committed rocprofv3 counter summary of the step kernel, if it was taken on the
+    current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -95,7 +95,22 @@ def load_traffic(name: str):
         return None
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d
+
+
+def load_traffic(name: str):
+    """HBM bytes per launch of the step kernel (calibrated FETCH_SIZE + WRITE_SIZE)."""
+    d = load_counters(name)
+    return None if d is None else d.get("hbm_bytes_per_launch")
+
+
+def load_l2_read(name: str):
+    """L2 read bytes per launch of the step kernel (TCC_READ_SECTORS x sector size)."""
+    d = load_counters(name)
+    if d is None or "l2" not in d:
+        return None
+    v = d["l2"]["read_bytes_per_launch"]
+    return sum(v) / len(v)
 
 
 def load_mfma_busy(name: str):
@@ -509,6 +524,14 @@ def main():
     ceil = gsb.gsb_device_ceilings()
     ceil["headline_frac_of_measured_fp4xfp8"] = achieved * 1e12 / ceil["mfma_fp4xfp8_flops"]
     out["ceilings"] = ceil
+    # L2 reads of the step kernel (operand fragments, read by each of the four product
+    # waves of a CU) against this device's measured streaming L2 read rate
+    l2 = load_l2_read("k_steps_ws_fp8_n2000_r1024_counters.json")
+    if l2 is not None:
+        rate = l2 / (k_ms * 1e-3)
+        out["roofline"]["l2_read"] = {"bytes_per_launch": l2, "achieved_Bps": rate,
+                                      "measured_peak_Bps": ceil["read_l2_2MiB_Bps"],
+                                      "frac": rate / ceil["read_l2_2MiB_Bps"]}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(J.astype(np.float64), c)
     print(json.dumps(out))
