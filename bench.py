@@ -420,7 +420,7 @@ def main():
     elapsed = time.perf_counter() - t0
     ms_per_step = 1000 * elapsed / args.steps
     rss = R * N * M / (elapsed / args.steps)
-    k_ms = float(np.mean(kernel_ms))
+    k_ms = float(np.median(kernel_ms))  # HIP-event time per launch, median over the timed launches
     flop = 2.0 * N * N * R * M  # algorithmic J.Q FLOP of one launch
     achieved = flop / (k_ms * 1e-3) / 1e12
 
