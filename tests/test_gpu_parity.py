@@ -212,6 +212,38 @@ def test_both_fp8_step_kernels_bitexact(orc, n):
         check_exact(x[sample], xo, "x"); check_exact(y[sample], yo, "y"); check_exact(p[sample], po, "p")
 
 
+@pytest.mark.parametrize("case", range(12))
+def test_fp8_kernels_on_seeded_random_shapes(orc, case):
+    # n, replicas, steps and variant drawn from a seeded generator: padded rows, padded
+    # replicas, one to several replica groups (padded grid or not), J partly in LDS or
+    # not, launches of one step.  Both FP8 step kernels, bit for bit with each other and
+    # with the oracle on sampled replicas.
+    rng = np.random.default_rng(1000 + case)
+    n = int(rng.integers(100, 2049))
+    R = int(rng.integers(1, 301))
+    M = int(rng.integers(1, 81))
+    variant = ["bsb", "dsb", "gbsb", "gdsb"][int(rng.integers(0, 4))]
+    A = float(rng.uniform(0.0, 0.5))
+    say(f"case random shapes #{case}: n={n} R={R} M={M} {variant} A={A:.3f}")
+    J = instances.dense_pm1(n, 50 + case)
+    c = instances.paper_c(n)
+    got = {}
+    for k in (1, 2):
+        g = gsb.GSB(J, precision="fp8", c=c, step_kernel=k)
+        g.run(variant, A=A, dt=1.25, replicas=R, steps=M, seed=case)
+        got[k] = g.state()[:3]
+        g.close()
+    for a, b, what in zip(got[1], got[2], ("x", "y", "p")):
+        check_exact(a, b, f"kernel 1 vs 2 {what}")
+    sample = np.unique(np.array([0, R // 2, R - 1]))
+    x0, y0, p0 = oracle_start(orc, n, R, case, orc.INIT_X)
+    form = orc.FORM_E4M3 if variant in ("bsb", "gbsb") else orc.FORM_EXACT
+    xo, yo, po = orc.run(J, orc.VARIANTS[variant], A=A, dt=1.25, c=c, steps=M, x=x0[sample], y=y0[sample],
+                         p=p0[sample], form=form, mode="fp32")
+    x, y, p = got[2]
+    check_exact(x[sample], xo, "x"); check_exact(y[sample], yo, "y"); check_exact(p[sample], po, "p")
+
+
 @pytest.mark.parametrize("precision,kernel,variant,form", [("fp8", 1, "gbsb", "e4m3"), ("fp8", 2, "gbsb", "e4m3"),
                                                             ("fix16", 0, "gbsb", "fix16"), ("fp32", 0, "gdsb", "exact")])
 def test_small_launch_on_padded_grid(orc, precision, kernel, variant, form):
