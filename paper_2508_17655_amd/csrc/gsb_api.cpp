@@ -444,6 +444,7 @@ gsb_status gsb_set(gsb_ctx* c, int32_t option, double v) {
       c->c_set = true;
       return GSB_OK;
     case GSB_OPT_PRECISION: {
+      if (!(v >= -1.0 && v <= 64.0)) return fail(GSB_EINVAL, "unknown precision");  // also NaN
       const int p = (int)v;
       if ((double)p != v || p < GSB_PREC_FP32 || p > GSB_PREC_FIX16) return fail(GSB_EINVAL, "unknown precision");
       if ((p == GSB_PREC_FP8 || p == GSB_PREC_FIX16) && !c->pm1)
@@ -455,12 +456,14 @@ gsb_status gsb_set(gsb_ctx* c, int32_t option, double v) {
       return GSB_OK;
     }
     case GSB_OPT_INIT_MODE: {
+      if (!(v >= -1.0 && v <= 64.0)) return fail(GSB_EINVAL, "unknown init mode");  // also NaN
       const int mm = (int)v;
       if ((double)mm != v || mm < GSB_INIT_X || mm > GSB_INIT_PAIRS) return fail(GSB_EINVAL, "unknown init mode");
       c->init_mode = mm;
       return GSB_OK;
     }
     case GSB_OPT_STEP_KERNEL: {
+      if (!(v >= 0.0 && v <= 2.0)) return fail(GSB_EINVAL, "step kernel must be 0, 1 or 2");  // also NaN
       const int k = (int)v;
       if ((double)k != v || k < 0 || k > 2) return fail(GSB_EINVAL, "step kernel must be 0, 1 or 2");
       if (k != c->kernel_pref) {

@@ -556,13 +556,23 @@ gsb_status gsb_batch_set_coupling(gsb_batch* b, int32_t k, const float* J, doubl
   return GSB_OK;
 }
 
+// An option value that must be an integer in [lo, hi]: false for anything else, NaN and
+// infinities included (checked before the conversion, which is undefined out of range).
+static bool int_option(double v, int lo, int hi, int* out) {
+  if (!(v >= (double)lo && v <= (double)hi)) return false;
+  const int iv = (int)v;
+  if ((double)iv != v) return false;
+  *out = iv;
+  return true;
+}
+
 gsb_status gsb_batch_set(gsb_batch* b, int32_t k, int32_t option, double v) {
   set_last_error("");
   if (!b) return bfail(GSB_EINVAL, "batch is NULL");
   if (option == GSB_BATCH_OCCUPANCY) {
     if (k != -1) return bfail(GSB_EINVAL, "batch-wide option: pass k = -1");
-    const int iv = (int)v;
-    if ((double)iv != v || iv < 0 || iv > 2) return bfail(GSB_EINVAL, "GSB_BATCH_OCCUPANCY is 0, 1 or 2");
+    int iv = 0;
+    if (!int_option(v, 0, 2, &iv)) return bfail(GSB_EINVAL, "GSB_BATCH_OCCUPANCY is 0, 1 or 2");
     if (iv) {
       gsb_status s = device_facts(b);
       if (s != GSB_OK) return s;
@@ -575,8 +585,8 @@ gsb_status gsb_batch_set(gsb_batch* b, int32_t k, int32_t option, double v) {
   }
   if (option == GSB_BATCH_GRAPH || option == GSB_BATCH_INIT_MODE) {
     if (k != -1) return bfail(GSB_EINVAL, "batch-wide option: pass k = -1");
-    const int iv = (int)v;
-    if ((double)iv != v) return bfail(GSB_EINVAL, "integer option");
+    int iv = 0;
+    if (!int_option(v, -1, 1 << 20, &iv)) return bfail(GSB_EINVAL, "integer option");
     if (option == GSB_BATCH_GRAPH) {
       if (iv != 0 && iv != 1) return bfail(GSB_EINVAL, "GSB_BATCH_GRAPH is 0 or 1");
       b->use_graph = iv == 1;
@@ -597,8 +607,9 @@ gsb_status gsb_batch_set(gsb_batch* b, int32_t k, int32_t option, double v) {
       drop_graph(b);
       return GSB_OK;
     case GSB_BATCH_TILE_ROWS: {
-      const int iv = (int)v;
-      if ((double)iv != v || (iv != 0 && tile_index(iv) < 0)) return bfail(GSB_EINVAL, "tile rows: 0, 64, 128 or 256");
+      int iv = 0;
+      if (!int_option(v, 0, 256, &iv) || (iv != 0 && tile_index(iv) < 0))
+        return bfail(GSB_EINVAL, "tile rows: 0, 64, 128 or 256");
       b->tile_fixed[k] = iv;
       drop_graph(b);
       return GSB_OK;

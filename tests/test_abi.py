@@ -68,8 +68,10 @@ def test_options_and_errors_without_device():
         gsb.gsb_set(ctx, gsb.GSB_OPT_C, 0.25)
         assert gsb.gsb_get(ctx, gsb.GSB_OPT_C) == 0.25
         assert gsb.gsb_get(ctx, gsb.GSB_OPT_STEP_KERNEL) == 0
-        for bad in (-1, 3, 1.5):
+        for bad in (-1, 3, 1.5, float("nan"), float("inf"), 1e300):
             assert _status(gsb.gsb_set, ctx, gsb.GSB_OPT_STEP_KERNEL, bad) == gsb.GSB_EINVAL
+            assert _status(gsb.gsb_set, ctx, gsb.GSB_OPT_PRECISION, bad if bad != 3 else 9) == gsb.GSB_EINVAL
+            assert _status(gsb.gsb_set, ctx, gsb.GSB_OPT_INIT_MODE, bad if bad != 3 else 9) == gsb.GSB_EINVAL
         gsb.gsb_set(ctx, gsb.GSB_OPT_STEP_KERNEL, 2)
         assert gsb.gsb_get(ctx, gsb.GSB_OPT_STEP_KERNEL) == 2
     finally:

@@ -81,6 +81,13 @@ def test_batch_arguments_are_checked_before_any_device_work():
         with pytest.raises(gsb.GsbError):
             gsb.gsb_batch_set(b, 0, gsb.GSB_BATCH_TILE_ROWS, 96)
         gsb.gsb_batch_set(b, 0, gsb.GSB_BATCH_TILE_ROWS, 128)
+        for bad in (float("nan"), float("inf"), -float("inf"), 1e300, 64.5):
+            with pytest.raises(gsb.GsbError):
+                gsb.gsb_batch_set(b, 0, gsb.GSB_BATCH_TILE_ROWS, bad)
+            with pytest.raises(gsb.GsbError):
+                gsb.gsb_batch_set(b, -1, gsb.GSB_BATCH_GRAPH, bad)
+            with pytest.raises(gsb.GsbError):
+                gsb.gsb_batch_set(b, -1, gsb.GSB_BATCH_INIT_MODE, bad)
         with pytest.raises(gsb.GsbError):
             gsb.gsb_batch_set(b, 0, gsb.GSB_BATCH_GRAPH, 1)  # batch-wide: k must be -1
         gsb.gsb_batch_set(b, -1, gsb.GSB_BATCH_GRAPH, 1)
