@@ -103,7 +103,15 @@ typedef enum {
                              per SIMD computes product and update (J in registers),
                              2 = two waves per SIMD, one computing the product (J in
                              registers and LDS), the other the update.  Other precisions
-                             and sizes ignore it.  Takes effect at the next gsb_init. */
+                             and sizes ignore it.  Takes effect at the next gsb_init. */,
+  GSB_OPT_GRID_PAD = 11   /* 1 (default): pad the grid of each time-stepping launch to a
+                             whole number of rounds of 8 replica groups when that still
+                             fits on the device (the padding workgroups exit at once), so
+                             that the workgroups of a group are dispatched to one XCD and
+                             exchange the operand through its L2; 0: no padding, a group's
+                             workgroups may sit on several XCDs and every step then goes
+                             through a group counter with device-scope fences (slower; the
+                             results are the same bits).  Takes effect at the next launch. */
 } gsb_option;
 
 /* Create a context for the instance (J, h).

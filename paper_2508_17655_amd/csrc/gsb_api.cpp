@@ -179,6 +179,7 @@ struct gsb_ctx {
   int precision = GSB_PREC_FP32;
   int init_mode = GSB_INIT_X;
   int kernel_pref = 0;  // GSB_OPT_STEP_KERNEL
+  int grid_pad = 1;     // GSB_OPT_GRID_PAD
   hipStream_t stream = nullptr;
   // run
   bool inited = false;
@@ -472,6 +473,11 @@ gsb_status gsb_set(gsb_ctx* c, int32_t option, double v) {
       }
       return GSB_OK;
     }
+    case GSB_OPT_GRID_PAD: {
+      if (!(v == 0.0 || v == 1.0)) return fail(GSB_EINVAL, "grid padding must be 0 or 1");  // also NaN
+      c->grid_pad = (int)v;
+      return GSB_OK;
+    }
     default:
       return fail(GSB_EINVAL, "unknown or read-only option " + std::to_string(option));
   }
@@ -492,6 +498,7 @@ gsb_status gsb_get(gsb_ctx* c, int32_t option, double* v) {
     case GSB_OPT_PRECISION: *v = c->precision; return GSB_OK;
     case GSB_OPT_INIT_MODE: *v = c->init_mode; return GSB_OK;
     case GSB_OPT_STEP_KERNEL: *v = c->kernel_pref; return GSB_OK;
+    case GSB_OPT_GRID_PAD: *v = c->grid_pad; return GSB_OK;
     case GSB_OPT_LAMBDA_MAX: ensure_eig(c); *v = c->lmax; return GSB_OK;
     case GSB_OPT_LAMBDA_MIN: ensure_eig(c); *v = c->lmin; return GSB_OK;
     case GSB_OPT_N: *v = c->n_user; return GSB_OK;
@@ -628,7 +635,7 @@ gsb_status launch_chunks(gsb_ctx* c, int form, int cols, bool discrete, float A,
     // pad the grid to whole XCD rounds of groups when that still fits (kernel launches only)
     if (!adjoint) {
       const int gp = (a.groups + 7) / 8 * 8;
-      a.gpad = (c->max_wg > 0 && gp * a.nb <= c->max_wg) ? gp : a.groups;
+      a.gpad = (c->grid_pad && c->max_wg > 0 && gp * a.nb <= c->max_wg) ? gp : a.groups;
     }
     HIP_TRY(launch_fill_u32(c->sync, sync_words(a.groups), 0u, c->stream), "clear sync");
     if (adjoint) {

@@ -143,14 +143,17 @@ __device__ __forceinline__ void encode_fix16x4(const float xv[4], unsigned& wh, 
   }
 }
 
+// fp8_tag (FP8 only) is ORed into the stored word: a step tag in bit 6 of its first byte,
+// which the E4M3 code of any |x| <= 1 leaves clear (exponent field at most 7).
 template <int FORM, bool DISC>
 __device__ __forceinline__ void store_operand(uint8_t* qbuf, size_t plane_bytes, int nks,
-                                              int ibase, int rcol, int lane, const float xv[4]) {
+                                              int ibase, int rcol, int lane, const float xv[4],
+                                              unsigned fp8_tag = 0u) {
   const int rb = rcol >> 4;
   const int kc = ibase >> 7;
   const int kk0 = (ibase & 127) + 4 * (lane >> 4);  // first of this lane's 4 rows
   if constexpr (FORM == kFormFP8) {
-    const unsigned w = encode_fp8x4<DISC>(xv);
+    const unsigned w = encode_fp8x4<DISC>(xv) | fp8_tag;
     const int lanep = (lane & 15) + 16 * (kk0 >> 5);
     const int half = (kk0 & 31) >> 4;
     const size_t off = ((size_t)(rb * nks + kc) * 2 + half) * 1024 + lanep * 16 + (kk0 & 15);

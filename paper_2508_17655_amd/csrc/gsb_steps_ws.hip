@@ -9,12 +9,21 @@
 //     the rest in LDS), runs the K loops of both 16-replica column tiles, alternately,
 //     and leaves each 64 x 16 product in an LDS slot;
 //   - update wave w (waves 4-7): takes the product from the slot, applies eqs. (7), (3),
-//     (4), (5) in binary32 (one rounding per operator), writes the next operand and
-//     counts itself in at that column tile's group counter.
+//     (4), (5) in binary32 (one rounding per operator) and writes the next operand.
 // The matrix cores and the vector ALU of a SIMD execute instructions of different waves
 // at the same time, so the update of one column tile runs under the K loop of the other.
-// The product waves meet (in LDS) only before each switch of operand, where one of them
-// polls the group counter for all four.
+//
+// Operand exchange.  Every operand word carries a tag of the step that wrote it, in bit 6
+// of its first byte (the E4M3 code of a value in [-1, 1] never sets that bit; the wall of
+// eq. (5) keeps x there).  Operand k (k = 0 at the launch's first step) sits in buffer
+// k % 2 with tag (k / 2) % 2, so a buffer holds either the operand a product wave wants or
+// the one two steps older, whose tag differs.  Each product wave strips and checks the tag
+// of every word it loads and loads again while any is stale: a word is written by one
+// 32-bit store and so is seen whole or not at all, and no group counter is needed between
+// steps.  The launch's first operand is behind the group counter (buffer 1 is cleared to
+// the stale tag under the same counter).  Where the group spans XCDs, whose L2 caches are
+// not coherent with each other, every step also goes through the group counter with
+// agent-scope fences, and the product waves meet in LDS where one of them polls it.
 #include "gsb_device.h"
 
 #pragma clang fp contract(off)
@@ -163,6 +172,53 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
       if (!local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       return true;
     };
+    // strip the step tag from fragments and report (for the whole wave) whether any of
+    // their words was stale: pat is the expected tag, cmask 0x40 (or 0: no check)
+    auto strip = [&](v8i& b, unsigned pat) -> unsigned {
+      unsigned o = 0;
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        b[d] ^= (int)pat;
+        o |= (unsigned)b[d];
+      }
+      return o;
+    };
+    auto any_stale = [&](unsigned o, unsigned cmask) -> bool {
+      return __builtin_amdgcn_ballot_w64((o & cmask) != 0u) != 0;
+    };
+    // the first kPF fragments of a K loop, loaded before it: checked together, and all
+    // loaded again while any word is stale (the common wait for the operand)
+    auto gate = [&](int sub, int buf, unsigned pat, unsigned cmask) -> bool {
+      unsigned o = 0;
+#pragma unroll
+      for (int u = 0; u < kPF; ++u) o |= strip(bq[u], pat);
+      if (__builtin_expect(!any_stale(o, cmask), 1)) return true;
+      unsigned spins = 0;
+      do {
+        if (!keep_polling(++spins, kSpinLimit, abort_flag, a.status)) return false;
+        __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+        for (int u = 0; u < kPF; ++u) load_b(sub, buf, u, bq[u]);
+        __builtin_amdgcn_s_waitcnt(0);
+        o = 0;
+#pragma unroll
+        for (int u = 0; u < kPF; ++u) o |= strip(bq[u], pat);
+      } while (any_stale(o, cmask));
+      return true;
+    };
+    // a later fragment: loaded again on its own while stale (other fragments in flight
+    // are left alone, so that their registers and the load counter stay as they are)
+    auto recheck = [&](int sub, int buf, int ks, unsigned pat, unsigned cmask) -> bool {
+      if (__builtin_expect(!any_stale(strip(bq[ks % kPF], pat), cmask), 1)) return true;
+      unsigned spins = 0;
+      do {
+        if (!keep_polling(++spins, kSpinLimit, abort_flag, a.status)) return false;
+        __builtin_amdgcn_s_sleep(1);
+        load_b(sub, buf, ks, bq[ks % kPF]);
+        __builtin_amdgcn_s_waitcnt(0);
+      } while (any_stale(strip(bq[ks % kPF], pat), cmask));
+      return true;
+    };
     auto load_jl = [&](int ks, v4i* dst) {
 #pragma unroll
       for (int rt = 0; rt < 4; ++rt)
@@ -197,6 +253,9 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
     if (alive) prefetch(0, 0);
     for (int s = 0; alive && s < steps; ++s) {
       const int cur = s & 1;
+      // the launch's first operand is behind the group counter and carries no tag
+      const unsigned cmask = s > 0 ? 0x40u : 0u;
+      const unsigned pat = ((s >> 1) & 1) ? cmask : 0u;
 #pragma unroll
       for (int sub = 0; sub < 2; ++sub) {
         const int seq = 2 * s + sub + 1;
@@ -214,6 +273,11 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
 #pragma unroll
         for (int ks = 0; ks < NKS; ++ks) {
           __builtin_amdgcn_sched_barrier(0);
+          if (ks == 0) {
+            if (alive) alive = gate(sub, cur, pat, cmask);
+          } else if (ks >= kPF) {
+            if (alive) alive = recheck(sub, cur, ks, pat, cmask);
+          }
           if constexpr (NL > 0) {
             if (ks >= NR && ks + 1 < NKS) load_jl(ks + 1, jl[(ks + 1 - NR) & 1]);
           }
@@ -229,6 +293,9 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
           asm volatile("" ::: "memory");
           __builtin_amdgcn_sched_barrier(0);
         }
+        if (!alive) break;
+        // within one XCD the next operand's first fragments travel during the hand-over
+        if (local && has_next) prefetch(sub ^ 1, nbuf);
         // hand the product to the update wave once it has read the previous one
         {
           unsigned spins = 0;
@@ -242,13 +309,15 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
           for (int rt = 0; rt < 4; ++rt) *reinterpret_cast<v4f*>(slot + (rt * 64 + lane) * 4) = acc[rt];
           __hip_atomic_store(&s_ready[w], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
-        // operand of the next K loop
-        __hip_atomic_fetch_add(&s_pw_arrived, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (has_next) {
-          alive = pw_sync(seq, nctr, ntarget);
-          if (alive) prefetch(sub ^ 1, nbuf);
+        // across XCDs, the operand of the next K loop is loaded behind the group counter
+        if (!local) {
+          __hip_atomic_fetch_add(&s_pw_arrived, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (has_next) {
+            alive = pw_sync(seq, nctr, ntarget);
+            if (alive) prefetch(sub ^ 1, nbuf);
+          }
+          if (!alive) break;
         }
-        if (!alive) break;
       }
     }
     return;
@@ -303,7 +372,7 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) t[e] = ys[sub][e >> 2][e & 3] - t[e];            // y + dy
   };
-  auto after = [&](int sub, const v4f* acc, uint8_t* qnext) {
+  auto after = [&](int sub, const v4f* acc, uint8_t* qnext, unsigned tag) {
     float u[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) u[e] = cdt * acc[e >> 2][e & 3];                 // Dy
@@ -321,7 +390,7 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt)
       store_operand<kFormFP8, DISC>(qnext, a.q_buf_bytes, NKS, row0 + rt * 16, col0 + sub * 16, lane,
-                                    xs[sub][rt]);
+                                    xs[sub][rt], tag);
   };
 
   bool alive = alive0;
@@ -329,15 +398,20 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
 #pragma unroll
     for (int sub = 0; sub < 2; ++sub)
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
+      for (int rt = 0; rt < 4; ++rt) {
+        // operand 0 untagged in buffer 0; buffer 1 holds the tag that operand 1 does not carry
         store_operand<kFormFP8, DISC>(a.q, a.q_buf_bytes, NKS, row0 + rt * 16, col0 + sub * 16, lane,
                                       xs[sub][rt]);
+        store_operand<kFormFP8, DISC>(a.q + a.q_buf_bytes, a.q_buf_bytes, NKS, row0 + rt * 16, col0 + sub * 16,
+                                      lane, xs[sub][rt], 0x40u);
+      }
     arrive(ctr0);
     arrive(ctr1);
   }
   for (int s = 0; alive && s < steps; ++s) {
     const int m = a.m_begin + s;
     uint8_t* qnext = a.q + (size_t)((s + 1) & 1) * a.q_buf_bytes;
+    const unsigned tag = ((s + 1) >> 1) & 1 ? 0x40u : 0u;  // operand s + 1
     const float rm = a.rtab[m];
 #pragma unroll
     for (int sub = 0; sub < 2; ++sub) {
@@ -352,8 +426,8 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
 #pragma unroll
       for (int rt = 0; rt < 4; ++rt) acc[rt] = *reinterpret_cast<const v4f*>(slot + (rt * 64 + lane) * 4);
       __hip_atomic_store(&s_taken[w], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-      after(sub, acc, qnext);
-      arrive(sub == 0 ? ctr0 : ctr1);
+      after(sub, acc, qnext, tag);
+      if (!local) arrive(sub == 0 ? ctr0 : ctr1);
     }
   }
 

@@ -24,7 +24,8 @@ GSB_SCHED_LINEAR, GSB_SCHED_CONSTANT = 0, 1
 GSB_PREC_FP32, GSB_PREC_BF16X2, GSB_PREC_FP8, GSB_PREC_FIX16 = 0, 1, 2, 3
 GSB_INIT_X, GSB_INIT_XY, GSB_INIT_PM01, GSB_INIT_PAIRS = 0, 1, 2, 3
 (GSB_OPT_C, GSB_OPT_PRECISION, GSB_OPT_INIT_MODE, GSB_OPT_LAMBDA_MAX, GSB_OPT_LAMBDA_MIN, GSB_OPT_N,
- GSB_OPT_STEP, GSB_OPT_REPLICAS, GSB_OPT_DT_STABLE, GSB_OPT_N_DYN, GSB_OPT_STEP_KERNEL) = range(11)
+ GSB_OPT_STEP, GSB_OPT_REPLICAS, GSB_OPT_DT_STABLE, GSB_OPT_N_DYN, GSB_OPT_STEP_KERNEL,
+ GSB_OPT_GRID_PAD) = range(12)
 
 (GSB_BATCH_C, GSB_BATCH_DT, GSB_BATCH_LAMBDA_MAX, GSB_BATCH_LAMBDA_MIN, GSB_BATCH_TILE_ROWS, GSB_BATCH_STEP_US,
  GSB_BATCH_N, GSB_BATCH_GRAPH, GSB_BATCH_INIT_MODE, GSB_BATCH_COUNT, GSB_BATCH_REPLICAS, GSB_BATCH_GRID,
@@ -509,7 +510,8 @@ class GSB:
     """
 
     def __init__(self, J: np.ndarray, h: np.ndarray | None = None, *, precision: str | None = None,
-                 c: float | None = None, init_mode: int | None = None, step_kernel: int | None = None):
+                 c: float | None = None, init_mode: int | None = None, step_kernel: int | None = None,
+                 grid_pad: bool | None = None):
         import torch  # device memory and streams only
 
         if not torch.cuda.is_available():
@@ -525,6 +527,8 @@ class GSB:
             gsb_set(self.ctx, GSB_OPT_INIT_MODE, init_mode)
         if step_kernel is not None:
             gsb_set(self.ctx, GSB_OPT_STEP_KERNEL, step_kernel)
+        if grid_pad is not None:
+            gsb_set(self.ctx, GSB_OPT_GRID_PAD, 1 if grid_pad else 0)
 
     def close(self):
         if self.ctx is not None:

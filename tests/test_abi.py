@@ -74,6 +74,11 @@ def test_options_and_errors_without_device():
             assert _status(gsb.gsb_set, ctx, gsb.GSB_OPT_INIT_MODE, bad if bad != 3 else 9) == gsb.GSB_EINVAL
         gsb.gsb_set(ctx, gsb.GSB_OPT_STEP_KERNEL, 2)
         assert gsb.gsb_get(ctx, gsb.GSB_OPT_STEP_KERNEL) == 2
+        assert gsb.gsb_get(ctx, gsb.GSB_OPT_GRID_PAD) == 1
+        for bad in (-1, 2, 0.5, float("nan"), float("inf")):
+            assert _status(gsb.gsb_set, ctx, gsb.GSB_OPT_GRID_PAD, bad) == gsb.GSB_EINVAL
+        gsb.gsb_set(ctx, gsb.GSB_OPT_GRID_PAD, 0)
+        assert gsb.gsb_get(ctx, gsb.GSB_OPT_GRID_PAD) == 0
     finally:
         gsb.gsb_destroy(ctx)
     ctx = gsb.gsb_create(instances.dense_gaussian(10, 2))

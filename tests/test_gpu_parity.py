@@ -244,6 +244,35 @@ def test_fp8_kernels_on_seeded_random_shapes(orc, case):
     check_exact(x[sample], xo, "x"); check_exact(y[sample], yo, "y"); check_exact(p[sample], po, "p")
 
 
+@pytest.mark.parametrize("n,R,variant", [(1500, 300, "gbsb"), (2000, 100, "dsb"), (700, 380, "gdsb")])
+def test_fp8_kernels_with_groups_across_xcds(orc, n, R, variant):
+    # Without grid padding, 4 or 12 replica groups put the row blocks of a group on
+    # different XCDs (workgroups go to the XCDs in turn), so the kernels take their
+    # cross-XCD exchange: a group counter with device-scope fences every step.  Both FP8
+    # step kernels, bit for bit with each other, with the padded grid and with the oracle.
+    M, A, seed = 60, 0.2, 9
+    say(f"case groups across XCDs n={n} R={R} M={M} {variant}")
+    J = instances.dense_pm1(n, 31)
+    c = instances.paper_c(n)
+    got = {}
+    for k, pad in ((1, False), (2, False), (2, True)):
+        g = gsb.GSB(J, precision="fp8", c=c, step_kernel=k, grid_pad=pad)
+        assert gsb.gsb_get(g.ctx, gsb.GSB_OPT_GRID_PAD) == (1 if pad else 0)
+        g.run(variant, A=A, dt=1.25, replicas=R, steps=M, seed=seed)
+        got[k, pad] = g.state()[:3]
+        g.close()
+    for key in ((1, False), (2, True)):
+        for a, b, what in zip(got[key], got[2, False], ("x", "y", "p")):
+            check_exact(a, b, f"{key} vs unpadded kernel 2, {what}")
+    sample = np.unique(np.array([0, 5, R // 2, R - 1]))
+    x0, y0, p0 = oracle_start(orc, n, R, seed, orc.INIT_X)
+    form = orc.FORM_E4M3 if variant in ("bsb", "gbsb") else orc.FORM_EXACT
+    xo, yo, po = orc.run(J, orc.VARIANTS[variant], A=A, dt=1.25, c=c, steps=M, x=x0[sample], y=y0[sample],
+                         p=p0[sample], form=form, mode="fp32")
+    x, y, p = got[2, False]
+    check_exact(x[sample], xo, "x"); check_exact(y[sample], yo, "y"); check_exact(p[sample], po, "p")
+
+
 @pytest.mark.parametrize("precision,kernel,variant,form", [("fp8", 1, "gbsb", "e4m3"), ("fp8", 2, "gbsb", "e4m3"),
                                                             ("fix16", 0, "gbsb", "fix16"), ("fp32", 0, "gdsb", "exact")])
 def test_small_launch_on_padded_grid(orc, precision, kernel, variant, form):
