@@ -381,8 +381,10 @@ gsb_status gsb_batch_plan(int32_t units, const int32_t* width, const int32_t* ga
  * out[0 .. min(count, 13) - 1] with, in order: dense MFMA rate in FLOP/s (OP/s for int8)
  * of the forms the step kernels use -- [0] FP8 x FP8 16x16x128, [1] FP4 x FP8 16x16x128,
  * [2] int8 16x16x64, [3] bf16 16x16x32, [4] binary32 16x16x4 -- from every CU running
- * 4 waves per SIMD of 8 independent MFMA chains; streaming read bandwidth in bytes/s over
- * [5] 2 MiB (L2), [6] 64 MiB (MALL), [7] 2 GiB (HBM); [8] streaming write bandwidth over
+ * 4 waves per SIMD of 8 independent MFMA chains; read bandwidth in bytes/s: [5] L2, over
+ * 2 MiB with device-scope (L1-skipping) 16-byte loads, four in flight per thread, 8
+ * workgroups of 256 threads per CU; streaming over [6] 64 MiB (MALL) and [7] 2 GiB (HBM);
+ * [8] streaming write bandwidth over
  * 2 GiB; [9] the shader clock in Hz during a busy kernel (s_memtime against the
  * constant-rate wall clock); then the 32 x 32 MFMA shapes: [10] FP8 x FP8 32x32x64,
  * [11] int8 32x32x32, [12] bf16 32x32x16.  Allocates and frees 2 GiB of device memory; runs on the null

@@ -1,9 +1,10 @@
 // gsb_probe.hip -- this device's ceilings, measured: the issue rate of each MFMA form the
-// step kernels use, streaming read bandwidth at L2-, MALL- and HBM-sized footprints, write
+// step kernels use, read bandwidth at L2-, MALL- and HBM-sized footprints, write
 // bandwidth, and the shader clock during a busy kernel.  The roofline fractions of the
 // step kernels are stated against the published peaks; these figures say how close to
 // them the chip itself gets.
 #include "gsb_internal.h"
+#include "gsb_device.h"
 
 #include <hip/hip_runtime.h>
 
@@ -87,6 +88,28 @@ __global__ void __launch_bounds__(256) k_stream_read(const v4f* p, size_t n4, in
   if (s[0] + s[1] + s[2] + s[3] == 1.2345e-30f) sink[blockIdx.x] = s[0];
 }
 
+// L2 read rate: device-scope 16-byte loads (they skip L1, as the step kernels' operand
+// loads do), four independent ones in flight per thread, at offsets that move by a
+// different amount on every round so that no CU reads its own lines again.  `mask` + 1
+// is the buffer's size, a power of two; every offset is a multiple of 16 within it.
+__global__ void __launch_bounds__(256) k_l2_read(const float* base, unsigned mask, int rounds, float* sink) {
+  const __amdgpu_buffer_rsrc_t r = make_rsrc(base, (size_t)mask + 1);
+  const unsigned t = (blockIdx.x * blockDim.x + threadIdx.x) * 16u;
+  v4f s0 = v4f{0.f, 0.f, 0.f, 0.f}, s1 = s0, s2 = s0, s3 = s0;
+  for (int k = 0; k < 4 * rounds; k += 4) {
+    const unsigned o0 = (t + (unsigned)(k + 0) * 0x9E3779B0u) & mask;
+    const unsigned o1 = (t + (unsigned)(k + 1) * 0x9E3779B0u) & mask;
+    const unsigned o2 = (t + (unsigned)(k + 2) * 0x9E3779B0u) & mask;
+    const unsigned o3 = (t + (unsigned)(k + 3) * 0x9E3779B0u) & mask;
+    s0 += __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(r, o0, 0, kPolicySc1));
+    s1 += __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(r, o1, 0, kPolicySc1));
+    s2 += __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(r, o2, 0, kPolicySc1));
+    s3 += __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(r, o3, 0, kPolicySc1));
+  }
+  const v4f s = s0 + s1 + s2 + s3;
+  if (s[0] + s[1] + s[2] + s[3] == 1.2345e-30f) sink[blockIdx.x] = s[0];
+}
+
 __global__ void __launch_bounds__(256) k_stream_write(v4f* p, size_t n4, int passes) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (int pass = 0; pass < passes; ++pass)
@@ -149,12 +172,27 @@ hipError_t measure_ceilings(double* out, int count) {
     if ((r = time_mfma<5>(blocks, 1000, sink, e0, e1, &v[10])) != hipSuccess) return r;
     if ((r = time_mfma<6>(blocks, 1000, sink, e0, e1, &v[11])) != hipSuccess) return r;
     if ((r = time_mfma<7>(blocks, 1000, sink, e0, e1, &v[12])) != hipSuccess) return r;
-    // streaming reads: 2 MiB (each XCD's L2 holds a copy), 64 MiB (MALL), 2 GiB (HBM)
+    // reads: 2 MiB (each XCD's L2 holds a copy; scattered device-scope loads, above),
+    // then streaming over 64 MiB (MALL) and 2 GiB (HBM)
     const v4f* p = static_cast<const v4f*>(buf);
     if ((r = hipMemset(buf, 0, big)) != hipSuccess) return r;
+    {
+      const unsigned grid = (unsigned)(cus * 8);  // sink holds more than cus * 8 floats
+      const unsigned mask = (2u << 20) - 1u;
+      const int rounds = 256;
+      hipLaunchKernelGGL(k_l2_read, dim3(grid), dim3(256), 0, 0, static_cast<const float*>(buf), mask, 4, sink);
+      if ((r = hipEventRecord(e0, 0)) != hipSuccess) return r;
+      hipLaunchKernelGGL(k_l2_read, dim3(grid), dim3(256), 0, 0, static_cast<const float*>(buf), mask, rounds, sink);
+      if ((r = hipGetLastError()) != hipSuccess) return r;
+      if ((r = hipEventRecord(e1, 0)) != hipSuccess) return r;
+      if ((r = hipEventSynchronize(e1)) != hipSuccess) return r;
+      float ms = 0;
+      if ((r = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return r;
+      v[5] = (double)grid * 256 * 16 * 4 * rounds / (ms * 1e-3);
+    }
     const size_t sizes[3] = {(size_t)2 << 20, (size_t)64 << 20, big};
     const int passes[3] = {400, 20, 2};
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 1; k < 3; ++k) {
       const size_t n4 = sizes[k] / 16;
       const unsigned grid = (unsigned)(cus * 8);
       hipLaunchKernelGGL(k_stream_read, dim3(grid), dim3(256), 0, 0, p, n4, 1, sink);
