@@ -244,6 +244,30 @@ def test_fp8_kernels_on_seeded_random_shapes(orc, case):
     check_exact(x[sample], xo, "x"); check_exact(y[sample], yo, "y"); check_exact(p[sample], po, "p")
 
 
+def test_chained_launches_on_full_size_operand(orc):
+    # The wave-specialised kernel's operand buffers keep their contents across launches
+    # and runs of a context; every launch restarts the step tags of its operand words.
+    # At n = 2000 (16 k-steps: first fragments checked together, later ones one by one),
+    # runs of one launch and of launches of 1 to 7 steps, repeated on one context, give
+    # the register-J kernel's bits.
+    n, R, M, seed = 2000, 128, 40, 12
+    say(f"case chained full size n={n} R={R} M={M}")
+    J = instances.dense_pm1(n, 8)
+    c = instances.paper_c(n)
+    g2 = gsb.GSB(J, precision="fp8", c=c, step_kernel=2)
+    g1 = gsb.GSB(J, precision="fp8", c=c, step_kernel=1)
+    g1.run("gbsb", A=0.2, dt=1.25, replicas=R, steps=M, seed=seed)
+    ref = g1.state()[:3]
+    g1.close()
+    for pieces in ((M,), (1, 2, 3, 4, 5, 6, 7, 12), (7, 7, 7, 7, 7, 5), (M,)):
+        g2.init("gbsb", A=0.2, dt=1.25, replicas=R, steps=M, seed=seed)
+        for k in pieces:
+            g2.step(k)
+        for a, b, what in zip(g2.state()[:3], ref, ("x", "y", "p")):
+            check_exact(a, b, f"pieces {pieces}: {what}")
+    g2.close()
+
+
 @pytest.mark.parametrize("n,R,variant", [(1500, 300, "gbsb"), (2000, 100, "dsb"), (700, 380, "gdsb")])
 def test_fp8_kernels_with_groups_across_xcds(orc, n, R, variant):
     # Without grid padding, 4 or 12 replica groups put the row blocks of a group on
