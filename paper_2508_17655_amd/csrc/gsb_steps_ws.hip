@@ -227,9 +227,10 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
 
     // the slot flag is read half way through the K loop (it has returned by its end)
     constexpr int kTakenAt = NKS / 2;
-    // The four product waves meet before each operand switch: wave 0 polls the group
-    // counter once all four have handed over their product, then all load (one poller per
-    // workgroup instead of four, and the four load the same fragments together).
+    // Where the group counter is needed (the launch's first operand; every operand switch
+    // when the group spans XCDs) the four product waves meet: wave 0 polls the counter once
+    // all four have handed over their product, then all load (one poller per workgroup
+    // instead of four, and the four load the same fragments together).
     auto pw_sync = [&](int seqv, unsigned* ctr, unsigned target) -> bool {
       bool ok = true;
       if (w == 0) {
