@@ -60,8 +60,9 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
   __shared__ int s_taken[4];  // sequence number of the last product update wave w read
   __shared__ int s_pw_arrived;  // product waves that have handed over their product
   __shared__ int s_pw_go;       // product waves may load the operand of this sequence number
-  constexpr int kPF = kKStepsUnroll;
-  static_assert(NKS % kPF == 0 && NKS >= kPF, "k-steps must be a multiple of the prefetch depth");
+  // operand fragments in flight per product wave (the K loop is fully unrolled, so the
+  // depth need not divide the k-steps); five is what the registers hold without spills
+  constexpr int kPF = NKS < 5 ? NKS : 5;
   constexpr int NR = NKS < kWsRegKSteps ? NKS : kWsRegKSteps;  // J k-steps in registers
   constexpr int NL = NKS - NR;                                 // J k-steps in LDS
 
