@@ -101,6 +101,40 @@ def test_bf16_rounding_matches_torch(orc):
     np.testing.assert_array_equal(orc.bf16_round(v), ref)
 
 
+def test_bf16x2_split_matches_torch(orc):
+    # The continuous operand of the BF16X2 form is hi + lo with hi = bf16(x) and
+    # lo = bf16(x - hi), both rounded by PyTorch's conversion here; x - hi is exact in
+    # binary32.  Two 8-bit significands give |x - (hi + lo)| <= 2^-18 |x| for normal
+    # values (2^-16 stated with margin), so a dropped lo plane, a lo of the wrong sign
+    # (bf16(hi - x)) or a lo taken from the unrounded x all fail.
+    rng = np.random.default_rng(11)
+    # dense over [-1, 1] (the range the wall keeps x in), every binade down to 2^-40, and
+    # residuals x - hi with nine significant bits ending in a half (ties to even in lo)
+    v = np.concatenate([np.linspace(-1.0, 1.0, 400001), rng.uniform(-1, 1, 400000),
+                        rng.choice([-1.0, 1.0], 100000) * 2.0 ** rng.uniform(-40, 0, 100000)]).astype(np.float32)
+    tie = ((rng.integers(0x3C00, 0x3F80, 20000).astype(np.uint32) << 16) | np.uint32(0x0181)).view(np.float32)
+    v = np.concatenate([v, tie, np.float32([0.0, -0.0, 1.0, -1.0])])
+    xt = torch.from_numpy(v)
+    hi = xt.to(torch.bfloat16).float()
+    lo = (xt - hi).to(torch.bfloat16).float()
+    ref = hi.double().numpy() + lo.double().numpy()
+    got = orc.operand(v, orc.FORM_BF16X2)
+    np.testing.assert_array_equal(got, ref)
+    err = np.abs(v.astype(np.float64) - got)
+    assert np.all(err <= 2.0**-16 * np.abs(v.astype(np.float64)))
+    # the split is not the identity: some values need the lo plane
+    assert np.count_nonzero(lo.numpy()) > 100000
+
+
+def test_spins_sign_of_zero(orc):
+    # eq. (1) needs s in {-1, +1}: sgn(0) is read as +1 for both zeros; the smallest
+    # subnormals keep their sign (a test of "x > 0" or of the sign bit fails here)
+    x32 = np.array([0.0, -0.0, -1e-45, 1e-45, -1.0, 1.0], dtype=np.float32)
+    assert orc.spins(x32).tolist() == [1, 1, -1, 1, -1, 1]
+    x64 = np.array([0.0, -0.0, -5e-324, 5e-324, -1.0, 1.0], dtype=np.float64)
+    assert orc.spins(x64).tolist() == [1, 1, -1, 1, -1, 1]
+
+
 # --------------------------------------------------------------------------------------
 # Energy (eq. (1)), cut (Sec. III) and the exhaustive ground state
 # --------------------------------------------------------------------------------------
@@ -383,3 +417,21 @@ def test_delta_definition(orc):
     assert orc.delta(np.ones(n), -np.ones(n)) == 1.0
     a, b = rng.choice([-1.0, 1.0], (2, 200000))
     assert abs(orc.delta(a, b) - 1 / math.sqrt(2)) < 5e-3
+
+
+def test_best_replica_first_of_equal_minima(orc):
+    # The best replica is the argmin of the energies with ties going to the lowest replica
+    # index (a reading: the paper reports the best energy, not which replica holds it).
+    # numpy's argmin returns the first occurrence; tie-heavy integer energies make a
+    # "<=" comparison (last occurrence) or an off-by-one start fail.
+    rng = np.random.default_rng(12)
+    for R in (1, 2, 3, 17, 128, 1000, 4096):
+        for _ in range(20):
+            E = rng.integers(-3, 3, R).astype(np.float64)
+            assert orc.best(E) == int(np.argmin(E))
+    E = np.full(64, -5.0)
+    assert orc.best(E) == 0
+    E[63] = -6.0
+    assert orc.best(E) == 63
+    E = np.array([2.0, -1.0, -1.0, 0.0, -1.0])
+    assert orc.best(E) == 1
