@@ -2,12 +2,17 @@
 
 One bench step = one whole pass of the hot path on a batch: gsb_run (initial state of
 1024 replicas, 2000 symplectic-Euler steps with the fused eq. (7)/(3)/(4)/(5) update, and
-the eq. (1) energies) followed by gsb_best (argmin and its spins).  The instance is a
-synthetic stand-in for K2000 (Sec. III): J_ij iid uniform on {-1, +1}, generated from a
-seed, already resident in HBM when timing starts.
+the eq. (1) energies) followed by gsb_best (argmin and its spins).  The timed form is GSB
+with individual control, eq. (7), on the sign product of dSB (GdSB, A = 0.2): its
+coupling sums are sums of +-1 terms, exact in the FP8 product and in the binary32 one, so
+the FP8 form computes the same bits as the FP32 form.  The instance is a synthetic
+stand-in for K2000 (Sec. III): J_ij iid uniform on {-1, +1}, generated from a seed,
+already resident in HBM when timing starts.  Reported beside it: the FP32 form of the same
+run, GbSB (continuous product) in the 16-bit fixed-point form (the paper's JX precision,
+exact) and with an E4M3-rounded operand, success probabilities and TTS99 (Sec. VI).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep] [--no-cpu] [--no-chaos]
-                    [--no-batch] [--no-dt]
+                    [--no-batch] [--no-dt] [--no-precision]
 
 Prints one JSON line.
 """
@@ -25,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 N, R, M, DT, A_HEAD, SEED_J = 2000, 1024, 2000, 1.25, 0.2, 2
+HEAD_VARIANT = "gdsb"  # the timed form: eq. (7) on the sign product, exact in FP8
 A_SWEEP = [0.05, 0.10, 0.15, 0.20, 0.25, 0.30, 0.35, 0.40]
 FP8_PEAK = 5.0e15      # MI355X dense FP8 MFMA, FLOP/s
 FP32_MFMA_PEAK = 157.3e12
@@ -34,18 +40,19 @@ PROFILE_RUNS = 13      # launches of the headline workload under a profiler (--p
 
 def tts99(t_com: float, p_run: float) -> float:
     """TTS = T_com ln(1 - 0.99)/ln(1 - P_S), or T_com when P_S > 0.99 (Sec. VI)."""
-    if p_run > 0.99:
-        return t_com
-    if p_run <= 0.0:
-        return math.inf
-    return t_com * math.log(0.01) / math.log(1.0 - p_run)
+    from paper_2508_17655_amd import stats
+
+    return stats.tts99(t_com, p_run)
 
 
 def tts_vs_replicas(g8, rows, sizes=(16, 128, 1024, 4096), reps=3):
     """TTS99 with the batch semantics (Sec. VI) for launches of R replicas of the FP8 form:
     T_com(R) is the measured wall time of one launch (run + best), P_S of the launch is
-    1 - (1 - p_hat)^R with the per-replica p_hat measured at R = 1024."""
+    1 - (1 - p_hat)^R with the per-replica p_hat measured at R = 1024, and dTTS propagates
+    the error of that p_hat."""
     import torch
+
+    from paper_2508_17655_amd import stats
     out = []
     for row in rows:
         for r in sizes:
@@ -58,11 +65,13 @@ def tts_vs_replicas(g8, rows, sizes=(16, 128, 1024, 4096), reps=3):
                 g8.best()
             torch.cuda.synchronize()
             t_com = (time.perf_counter() - t0) / reps
-            p_run = 1.0 - (1.0 - row["p_hat"]) ** r
+            p_run = stats.p_run(row["p_hat"], r)
+            t = stats.tts99(t_com, p_run)
             out.append({"variant": row["variant"], "A": row["A"], "replicas": r, "p_hat": row["p_hat"],
                         "t_com_s": t_com, "us_per_step": 1e6 * t_com / M,
                         "replica_spin_steps_per_s": r * N * M / t_com, "p_run": p_run,
-                        "tts99_s": _finite(tts99(t_com, p_run))})
+                        "tts99_s": _finite(t), "dtts99_s": _finite(stats.dtts(t, row["p_hat"], row["dp_hat"]))
+                        if p_run <= stats.TARGET else 0.0})
     return out
 
 
@@ -94,7 +103,7 @@ def load_counters(name: str):
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+    if d.get("kernel_source_sha256_16") != kernel_source_hash() or d.get("variant") != HEAD_VARIANT:
         return None
     return d
 
@@ -117,40 +126,155 @@ def load_l2_read(name: str):
 def load_mfma_busy(name: str):
     """Fraction of SIMD-cycles the matrix cores were busy during the step kernel, from the
     committed rocprofv3 counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", name)
+    d = load_counters(name)
+    return None if d is None else d.get("mfma_busy_frac")
+
+
+def _cpu_model() -> str:
     try:
-        with open(path) as f:
-            d = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if d.get("kernel_source_sha256_16") != kernel_source_hash():
-        return None
-    return d.get("mfma_busy_frac")
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def cpu_baseline(J, c, target_s: float = 12.0):
-    """The oracle as it stands (strict binary32 update, E4M3 product, the FP8 form's
-    arithmetic) on a bounded sample of the same run: all host threads, one replica each."""
-    import numpy as np
-
+def _oracle_rate(J, c, threads: int, target_s: float):
+    """Replica-spin-steps/s of the oracle on `threads` host threads, over a bounded sample
+    of the headline run: one replica per thread, as many of the M steps (and then as many
+    whole runs of M steps) as fill about target_s seconds."""
     import oracle
 
-    threads = oracle.num_threads()
+    oracle.set_num_threads(threads)
     x0, y0 = oracle.init_state(N, threads, 7)
     t0 = time.perf_counter()
-    oracle.run(J, oracle.GBSB, A=A_HEAD, dt=DT, c=c, steps=M, x=x0, y=y0, m_end=2, form=oracle.FORM_E4M3,
+    oracle.run(J, oracle.VARIANTS[HEAD_VARIANT], A=A_HEAD, dt=DT, c=c, steps=M, x=x0, y=y0, m_end=2,
                mode="fp32")
     per_step = (time.perf_counter() - t0) / 2  # one step of `threads` replicas
     want = max(4, int(target_s / max(per_step, 1e-6)))
     reps, steps = (threads, want) if want <= M else (threads * math.ceil(want / M), M)
     x0, y0 = oracle.init_state(N, reps, 7)
     t0 = time.perf_counter()
-    oracle.run(J, oracle.GBSB, A=A_HEAD, dt=DT, c=c, steps=M, x=x0, y=y0, m_end=steps, form=oracle.FORM_E4M3,
+    oracle.run(J, oracle.VARIANTS[HEAD_VARIANT], A=A_HEAD, dt=DT, c=c, steps=M, x=x0, y=y0, m_end=steps,
                mode="fp32")
     el = time.perf_counter() - t0
-    return {"value": reps * N * steps / el, "unit": "replica-spin-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{reps} replicas x {steps} of the {M} steps (GbSB, A={A_HEAD}, E4M3 product, strict "
-                      f"binary32 update) of the N={N} instance, {el:.1f} s"}
+    return reps * N * steps / el, reps, steps, el
+
+
+def config1_fp64():
+    """The small plain workload computed by the oracle in binary64: fully connected N = 200
+    +-1 instance (seed 1), h = 0, 16 replicas, 1000 steps, dt = 0.5, linear schedule,
+    x and y ~ U(-0.1, 0.1); best energy per variant (bSB, dSB, GbSB with A = 0.2)."""
+    import numpy as np
+
+    import oracle
+    from paper_2508_17655_amd import instances
+
+    n, reps, steps, dt = 200, 16, 1000, 0.5
+    J = instances.dense_pm1(n, 1).astype(np.float64)
+    c = instances.paper_c(n)
+    x0, y0 = oracle.init_state(n, reps, 1, oracle.INIT_XY)
+    out = {"n": n, "replicas": reps, "steps": steps, "dt": dt, "c": c, "init": "x, y ~ U(-0.1, 0.1)",
+           "seed_J": 1, "seed_init": 1}
+    t0 = time.perf_counter()
+    for name, A in (("bsb", 0.0), ("dsb", 0.0), ("gbsb", 0.2)):
+        x = oracle.run(J, oracle.VARIANTS[name], A=A, dt=dt, c=c, steps=steps, x=x0, y=y0, mode="fp64")[0]
+        E = oracle.energy(J, oracle.spins(x))
+        out[name] = {"A": A, "best": float(E.min()), "replica": oracle.best(E), "mean": float(E.mean())}
+    out["s"] = time.perf_counter() - t0
+    return out
+
+
+def errors_vs_fp64(J, c):
+    """Measured error of the forms whose product is not exact, against the oracle's binary64
+    run from the same start (the device draws the oracle's starting state bit for bit).
+      +-1 J, bSB, BF16X2 and FP32 forms: max over replicas of |x - x64| / |x64| after one
+        step from the start, after one step from the binary64 state at m = 99 (rounded to
+        binary32), and the largest over the first 100 steps of one run;
+      real J (N(0,1)/sqrt(N)), GbSB A = 0.2, BF16X2 form with bf16 J, full 2000-step run:
+        relative error of each replica's final energy and the fraction of replicas whose
+        spins agree (up to a global flip), against binary64 runs with the exact J and with
+        the bf16-rounded J."""
+    import numpy as np
+
+    import oracle
+    from paper_2508_17655_amd import gsb, instances
+
+    out = {}
+    reps, seed, m_chk = 4, 31, 100
+    x0, y0 = oracle.init_state(N, reps, seed)
+    # traj[:, k] is the state after k + 1 steps
+    traj = oracle.run(J, oracle.BSB, dt=DT, c=c, steps=M, x=x0, y=y0, m_end=m_chk, mode="fp64", record=True)[3]
+    x99, y99, p99 = (v.astype(np.float32) for v in
+                     oracle.run(J, oracle.BSB, dt=DT, c=c, steps=M, x=x0, y=y0, m_end=m_chk - 1, mode="fp64"))
+    one99 = oracle.run(J, oracle.BSB, dt=DT, c=c, steps=M, x=x99, y=y99, p=p99, m_begin=m_chk - 1,
+                       m_end=m_chk, mode="fp64")[0]
+
+    def rel(a, b):
+        return float(np.max(np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)))
+
+    for form in ("bf16x2", "fp32"):
+        g = gsb.GSB(J, precision=form, c=c)
+        g.init("bsb", dt=DT, replicas=reps, steps=M, seed=seed)
+        worst, first = 0.0, None
+        for m in range(m_chk):
+            g.step(1)
+            e = rel(g.state()[0].astype(np.float64), traj[:, m, :])
+            first = e if first is None else first
+            worst = max(worst, e)
+        g.set_state(x99, y99, p99, m_chk - 1)
+        g.step(1)
+        e99 = rel(g.state()[0].astype(np.float64), one99)
+        g.close()
+        out[f"bsb_{form}"] = {"one_step_from_start": first, "one_step_from_m99": e99,
+                              "max_over_first_100_steps": worst, "replicas": reps}
+    # real-weighted instance, full run
+    reps_r, seed_r, A = 16, 41, A_HEAD
+    Jg = instances.dense_gaussian(N, 3)
+    g = gsb.GSB(Jg, precision="bf16x2")
+    dt_r, c_r = g.get(gsb.GSB_OPT_DT_STABLE), None
+    g.run("gbsb", A=A, dt=dt_r, replicas=reps_r, steps=M, seed=seed_r)
+    c_r = g.get(gsb.GSB_OPT_C)
+    E_dev = g.energy()
+    s_dev = g.spins()
+    g.close()
+    x0, y0 = oracle.init_state(N, reps_r, seed_r)
+    J64 = Jg.astype(np.float64)
+    rows = {}
+    for name, Jref in (("exact_J", J64), ("bf16_J", oracle.bf16_round(Jg).astype(np.float64))):
+        x = oracle.run(Jref, oracle.GBSB, A=A, dt=dt_r, c=c_r, steps=M, x=x0, y=y0, mode="fp64")[0]
+        s_ref = oracle.spins(x)
+        E_ref = oracle.energy(J64, s_ref)  # energies of eq. (1) with the exact couplings
+        re = np.abs(E_dev - E_ref) / np.abs(E_ref)
+        agree = [bool(np.array_equal(s_dev[r], s_ref[r]) or np.array_equal(s_dev[r], -s_ref[r]))
+                 for r in range(reps_r)]
+        rows[name] = {"energy_rel_err_max": float(re.max()), "energy_rel_err_median": float(np.median(re)),
+                      "spins_agree_frac": float(np.mean(agree)),
+                      "best_rel_err": float(abs(E_dev.min() - E_ref.min()) / abs(E_ref.min()))}
+    out["real_J_gbsb_bf16x2"] = {"replicas": reps_r, "steps": M, "A": A, "dt": dt_r, "c": c_r, **rows}
+    return out
+
+
+def cpu_baseline(J, c, target_s: float = 12.0):
+    """The oracle as it stands (strict binary32 update and the exact sign product: the
+    arithmetic the headline form computes) on a bounded sample of the same run, on all host
+    threads (one replica each) and on one thread; the host CPU model."""
+    import numpy as np
+
+    import oracle
+
+    J = J.astype(np.float64)
+    threads = oracle.num_threads()
+    rate, reps, steps, el = _oracle_rate(J, c, threads, target_s)
+    rate1, reps1, steps1, el1 = _oracle_rate(J, c, 1, target_s / 3)
+    oracle.set_num_threads(threads)
+    return {"value": rate, "unit": "replica-spin-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} replicas x {steps} of the {M} steps ({HEAD_VARIANT}, A={A_HEAD}, sign product, "
+                      f"strict binary32 update) of the N={N} instance, {el:.1f} s",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "one_core": {"value": rate1, "sample": f"{reps1} replica x {steps1} steps, {el1:.1f} s"}}
 
 
 def chaos_sweeps(J, c):
@@ -196,6 +320,7 @@ def chaos_sweeps(J, c):
 
 
 BATCH_COUNT, BATCH_R, BATCH_M, BATCH_A = 256, 128, 1000, 0.2
+BATCH_VARIANT = "gdsb"  # exact sign product (the batch runs the FP8 product only)
 
 
 def batched_setup(specs):
@@ -218,7 +343,7 @@ def batched_uneven(seed: int = 1):
     in [64, 4096], even indices dense +-1 (c = 1/(2 sqrt n), dt = 1.25, App. A), odd
     indices Erdos-Renyi with p ~ U[0.01, 0.06] and +-1 weights (c = 1/lambda_max and
     eq. (13) dt from the library's Lanczos estimate), 128 replicas each, 1000 steps of
-    GbSB (A = 0.2), FP8 product.  Tiles are autotuned on the device; the timed runs replay
+    GdSB (A = 0.2; the sign product, exact in FP8).  Tiles are autotuned on the device; the timed runs replay
     one HIP graph (starting states, the persistent step kernel, energies and best)."""
     import numpy as np
     import torch
@@ -231,17 +356,17 @@ def batched_uneven(seed: int = 1):
     b = batched_setup(specs)
     setup_s = time.perf_counter() - t0
     t0 = time.perf_counter()
-    b.autotune("gbsb", A=A, trial_steps=50, seed=1)
+    b.autotune(BATCH_VARIANT, A=A, trial_steps=50, seed=1)
     tune_s = time.perf_counter() - t0
-    b.run("gbsb", A=A, steps=steps, seed=seed)  # eager: the step kernel alone is timed
+    b.run(BATCH_VARIANT, A=A, steps=steps, seed=seed)  # eager: the step kernel alone is timed
     torch.cuda.synchronize()
     kernel_ms = b.last_ms()
     b.set(-1, gsb.GSB_BATCH_GRAPH, 1)
-    b.run("gbsb", A=A, steps=steps, seed=seed)  # capture
+    b.run(BATCH_VARIANT, A=A, steps=steps, seed=seed)  # capture
     torch.cuda.synchronize()
     graph_ms = []
     for _ in range(3):
-        b.run("gbsb", A=A, steps=steps, seed=seed)
+        b.run(BATCH_VARIANT, A=A, steps=steps, seed=seed)
         graph_ms.append(b.last_ms())
     e_best, _ = b.best()
     ns = np.array([s_[1] for s_ in specs], dtype=np.float64)
@@ -255,7 +380,7 @@ def batched_uneven(seed: int = 1):
     flop = 2.0 * float(np.sum(ns ** 2)) * reps * steps
     gms = float(np.mean(graph_ms))
     return {"workload": f"{count} instances, n iid U[64, 4096] (sum n = {int(ns.sum())}), half dense +-1, half "
-                        f"Erdos-Renyi p~U[0.01,0.06] +-1, {reps} replicas x {steps} steps, GbSB A={A}, FP8 product",
+                        f"Erdos-Renyi p~U[0.01,0.06] +-1, {reps} replicas x {steps} steps, GdSB A={A}, FP8 sign product (exact)",
             "value": float(ns.sum()) * reps * steps / (gms * 1e-3), "unit": "replica-spin-steps/s",
             "ms_per_run": gms, "run": "HIP graph: starting states + persistent step kernel + energies + best",
             "kernel_ms": kernel_ms,
@@ -298,8 +423,8 @@ def precision_forms(J, c):
                     "unit": "replica-spin-steps/s", "peak_frac": executed / (ms * 1e-3) / peak,
                     "best": float(E.min()), "dt": dt})
     return {"replicas": reps, "steps": steps, "n": N, "A": A_HEAD, "rows": out,
-            "errors": "stated by tests: sign/E4M3 forms bit-exact; BF16X2 one step within 1e-5 (+-1 J) and "
-                      "dy within 4e-3 (real J, bf16-rounded couplings) of binary64"}
+            "errors": "sign and E4M3 forms: bit-exact with the oracle (tests); BF16X2, FP32 and real-J errors "
+                      "against binary64 measured in cpu_baseline.errors_vs_fp64"}
 
 
 def dt_study(J, c):
@@ -367,56 +492,67 @@ def main():
     torch.cuda.set_device(0)
     if args.profile_batch:
         b = batched_setup(instances.batch_workload(BATCH_COUNT, 1))
-        b.autotune("gbsb", A=BATCH_A, trial_steps=50, seed=1)
+        b.autotune(BATCH_VARIANT, A=BATCH_A, trial_steps=50, seed=1)
         for s in range(2):
-            b.run("gbsb", A=BATCH_A, steps=BATCH_M, seed=1 + s)
+            b.run(BATCH_VARIANT, A=BATCH_A, steps=BATCH_M, seed=1 + s)
         torch.cuda.synchronize()
         b.close()
-        print(json.dumps({"profile_runs": 2, "batch": BATCH_COUNT}))
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_runs": 2, "batch": BATCH_COUNT, "variant": BATCH_VARIANT}), flush=True)
         return
     J = instances.dense_pm1(N, SEED_J)
     c = instances.paper_c(N)
     g8 = gsb.GSB(J, precision="fp8", c=c)
 
-    if args.profile_small:
-        # small launches: three of 16 replicas, then three of 128, then the streaming
-        # kernel of known size that scales the byte counters
-        for r_small in (16, 128):
-            for s in range(3):
-                g8.run("gbsb", A=A_HEAD, dt=DT, replicas=r_small, steps=M, seed=300 + s)
-                g8.best()
+    def copy_kernel():
+        # a plain streaming kernel of known size (reads and writes 256 MiB each), for
+        # scaling the byte counters (a same-dtype copy_ would go to the DMA engine)
         a = torch.zeros(64 * 2**20, dtype=torch.int32, device="cuda")
         b = torch.empty_like(a)
         for _ in range(3):
             torch.add(a, 1, out=b)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_runs": 6, "replicas": [16, 128], "copy_bytes": a.numel() * 4}))
+        return a.numel() * 4
+
+    if args.profile_small:
+        # small launches: three of 16 replicas, then three of 128, then the copy kernel
+        for r_small in (16, 128):
+            for s in range(3):
+                g8.run(HEAD_VARIANT, A=A_HEAD, dt=DT, replicas=r_small, steps=M, seed=300 + s)
+                g8.best()
+        nbytes = copy_kernel()
+        g8.close()
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_runs": 6, "variant": HEAD_VARIANT, "replicas": [16, 128], "copy_bytes": nbytes}),
+              flush=True)
         return
     if args.profile:
         # as many launches as the default timed run (3 warm-up + 10): the clocks settle
-        # over the first few, and the profile's steady mean is then comparable
+        # over the first few, and the profile's steady mean is then comparable; then the
+        # FIX16 form (GbSB, the paper's JX precision) and the copy kernel
         for s in range(PROFILE_RUNS):
-            g8.run("gbsb", A=A_HEAD, dt=DT, replicas=R, steps=M, seed=100 + s)
+            g8.run(HEAD_VARIANT, A=A_HEAD, dt=DT, replicas=R, steps=M, seed=100 + s)
             g8.best()
-        # a plain streaming kernel of known size (reads and writes 256 MiB each), for
-        # scaling the HBM byte counters (a same-dtype copy_ would go to the DMA engine)
-        a = torch.zeros(64 * 2**20, dtype=torch.int32, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            torch.add(a, 1, out=b)
-        torch.cuda.synchronize()
-        print(json.dumps({"profile_runs": PROFILE_RUNS, "copy_bytes": a.numel() * 4}))
+        g8.close()
+        g16 = gsb.GSB(J, precision="fix16", c=c)
+        for s in range(5):
+            g16.run("gbsb", A=A_HEAD, dt=DT, replicas=R, steps=M, seed=200 + s)
+            g16.best()
+        g16.close()
+        nbytes = copy_kernel()
+        print(json.dumps({"profile_runs": PROFILE_RUNS, "variant": HEAD_VARIANT, "fix16_runs": 5,
+                          "copy_bytes": nbytes}), flush=True)
         return
 
-    # ---- timed region: the headline form (GbSB, FP8 E4M3 product) ----
+    # ---- timed region: the headline form (GdSB, exact FP8 sign product) ----
     for s in range(args.warmup):
-        g8.run("gbsb", A=A_HEAD, dt=DT, replicas=R, steps=M, seed=1000 + s)
+        g8.run(HEAD_VARIANT, A=A_HEAD, dt=DT, replicas=R, steps=M, seed=1000 + s)
         g8.best()
     torch.cuda.synchronize()
     kernel_ms = []
     t0 = time.perf_counter()
     for s in range(args.steps):
-        g8.run("gbsb", A=A_HEAD, dt=DT, replicas=R, steps=M, seed=2000 + s)
+        g8.run(HEAD_VARIANT, A=A_HEAD, dt=DT, replicas=R, steps=M, seed=2000 + s)
         g8.best()
         kernel_ms.append(g8.last_step_ms())
     torch.cuda.synchronize()
@@ -427,43 +563,49 @@ def main():
     flop = 2.0 * N * N * R * M  # algorithmic J.Q FLOP of one launch
     achieved = flop / (k_ms * 1e-3) / 1e12
 
-    # ---- the FP32 form of the same run (comparison, not the headline) ----
-    g32 = gsb.GSB(J, precision="fp32", c=c)
-    g32.run("gbsb", A=A_HEAD, dt=DT, replicas=R, steps=M, seed=999)
-    g32.best()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    nrep32 = 2
-    k32 = []
-    for s in range(nrep32):
-        g32.run("gbsb", A=A_HEAD, dt=DT, replicas=R, steps=M, seed=3000 + s)
-        g32.best()
-        k32.append(g32.last_step_ms())
-    torch.cuda.synchronize()
-    ms32 = 1000 * (time.perf_counter() - t1) / nrep32
-    fp32_form = {"value": R * N * M / (ms32 * 1e-3), "unit": "replica-spin-steps/s", "ms_per_run": ms32,
-                 "kernel_ms": float(np.mean(k32)),
-                 "mfma_frac": flop / (float(np.mean(k32)) * 1e-3) / FP32_MFMA_PEAK}
+    def timed(g, variant, seed0, reps=2):
+        g.run(variant, A=A_HEAD, dt=DT, replicas=R, steps=M, seed=seed0)
+        g.best()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ks = []
+        for s in range(reps):
+            g.run(variant, A=A_HEAD, dt=DT, replicas=R, steps=M, seed=seed0 + 1 + s)
+            g.best()
+            ks.append(g.last_step_ms())
+        torch.cuda.synchronize()
+        return 1000 * (time.perf_counter() - t1) / reps, float(np.mean(ks))
 
-    # ---- the 16-bit fixed-point form (exact continuous product, two int8 passes) ----
+    # ---- the FP32 form of the same run: the same bits, on binary32 MFMA ----
+    g32 = gsb.GSB(J, precision="fp32", c=c)
+    ms32, k32 = timed(g32, HEAD_VARIANT, 3000)
+    g8.run(HEAD_VARIANT, A=A_HEAD, dt=DT, replicas=R, steps=M, seed=3002)
+    g32.run(HEAD_VARIANT, A=A_HEAD, dt=DT, replicas=R, steps=M, seed=3002)
+    same_bits = bool(np.array_equal(g8.state()[0], g32.state()[0]))
+    fp32_form = {"variant": HEAD_VARIANT, "value": R * N * M / (ms32 * 1e-3), "unit": "replica-spin-steps/s",
+                 "ms_per_run": ms32, "kernel_ms": k32, "mfma_frac": flop / (k32 * 1e-3) / FP32_MFMA_PEAK,
+                 "state_bit_identical_to_fp8": same_bits, "fp8_speedup": ms32 / ms_per_step}
+
+    # ---- GbSB (continuous product) in the 16-bit fixed-point form: the paper's JX precision,
+    # exact (two int8 passes, exact int32 sums) ----
     g16 = gsb.GSB(J, precision="fix16", c=c)
-    g16.run("gbsb", A=A_HEAD, dt=DT, replicas=R, steps=M, seed=998)
-    g16.best()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    k16 = []
-    for s in range(nrep32):
-        g16.run("gbsb", A=A_HEAD, dt=DT, replicas=R, steps=M, seed=3100 + s)
-        g16.best()
-        k16.append(g16.last_step_ms())
-    torch.cuda.synchronize()
-    ms16 = 1000 * (time.perf_counter() - t1) / nrep32
-    fix16_form = {"value": R * N * M / (ms16 * 1e-3), "unit": "replica-spin-steps/s", "ms_per_run": ms16,
-                  "kernel_ms": float(np.mean(k16)),
-                  "int8_mfma_frac": 2 * flop / (float(np.mean(k16)) * 1e-3) / INT8_PEAK}
+    ms16, k16 = timed(g16, "gbsb", 3100)
+    fix16_form = {"variant": "gbsb", "value": R * N * M / (ms16 * 1e-3), "unit": "replica-spin-steps/s",
+                  "ms_per_run": ms16, "kernel_ms": k16,
+                  "roofline": {"bound": "mfma", "achieved": flop / (k16 * 1e-3) / 1e12, "peak": INT8_PEAK / 1e12,
+                               "unit": "TOP/s", "frac": flop / (k16 * 1e-3) / INT8_PEAK,
+                               "frac_executed": 2 * flop / (k16 * 1e-3) / INT8_PEAK,
+                               "note": "frac counts the algorithmic 2 N^2 R M once; the form executes two int8 passes"}}
+    # ---- GbSB with the operand rounded to E4M3 (narrower than the paper's JX) ----
+    mse, kse = timed(g8, "gbsb", 3200)
+    e4m3_form = {"variant": "gbsb", "value": R * N * M / (mse * 1e-3), "unit": "replica-spin-steps/s",
+                 "ms_per_run": mse, "kernel_ms": kse, "mfma_frac": flop / (kse * 1e-3) / FP8_PEAK,
+                 "note": "x rounded to OCP E4M3 for the product only: 3 mantissa bits, narrower than the "
+                         "16-bit fixed point of the paper's JX; bit-exact against the oracle's E4M3 mode"}
 
     out = {
-        "metric": "replica-spin-steps/s (GSB = GbSB, FP8 E4M3 product) at N=2000 dense +-1; TTS99; FP8 vs FP32 form",
+        "metric": "replica-spin-steps/s (GSB with the dSB sign product, GdSB A=0.2, exact in FP8) at N=2000 "
+                  "dense +-1; TTS99; FP8 vs FP32 form",
         "value": rss,
         "unit": "replica-spin-steps/s",
         "n_gpus": 1,
@@ -475,45 +617,71 @@ def main():
         "vs_baseline": None,
         "dtype": "fp8",
         "data": "synthetic",
-        "config": {"workload": f"dense +-1 Ising N={N} (K2000 stand-in), GbSB A={A_HEAD}, {R} replicas x {M} steps, "
-                               f"dt={DT}, c=1/(2 sqrt N), FP8 E4M3 product, binary32 update",
-                   "n": N, "replicas": R, "steps_per_run": M, "dt": DT, "A": A_HEAD, "instance_seed": SEED_J},
+        "config": {"workload": f"dense +-1 Ising N={N} (K2000 stand-in), GdSB (eq. (7) control on the dSB sign "
+                               f"product) A={A_HEAD}, {R} replicas x {M} steps, dt={DT}, c=1/(2 sqrt N); "
+                               f"FP8 E4M3 sign product (exact: sums of +-1), binary32 update",
+                   "n": N, "replicas": R, "steps_per_run": M, "dt": DT, "A": A_HEAD, "variant": HEAD_VARIANT,
+                   "instance_seed": SEED_J},
         "fp32_form": fp32_form,
-        "fix16_form": fix16_form,
+        "fix16_gbsb": fix16_form,
+        "e4m3_gbsb": e4m3_form,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP8_PEAK / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved * 1e12 / FP8_PEAK, "traffic": load_traffic("k_steps_ws_fp8_n2000_r1024_counters.json"),
+                     "frac": achieved * 1e12 / FP8_PEAK,
+                     "traffic": load_traffic("k_steps_ws_fp8_n2000_r1024_counters.json"),
                      "mfma_busy_frac_counters": load_mfma_busy("k_steps_ws_fp8_n2000_r1024_mfma_counters.json"),
-                     "kernel": "k_steps_ws<16> (FP8 product, J resident in VGPRs and LDS; product and update in separate waves)", "kernel_ms_per_launch": k_ms,
+                     "kernel": "k_steps_ws<16, sign> (FP8 product, J resident in VGPRs and LDS; product and update "
+                               "in separate waves)", "kernel_ms_per_launch": k_ms,
                      "flop_per_launch": flop},
     }
 
     # ---- success probability and TTS99 (Sec. VI definitions), FP8 vs FP32 form ----
     if not args.no_sweep:
+        from paper_2508_17655_amd import stats
+
         runs = []
-        t_com = {"fp8": ms_per_step * 1e-3, "fp32": ms32 * 1e-3, "fix16": ms16 * 1e-3}
-        for form, g in (("fp8", g8), ("fp32", g32), ("fix16", g16)):
-            for variant, A in [("bsb", 0.0)] + [("gbsb", a) for a in A_SWEEP]:
+        t_com = {("fp8", "sign"): ms_per_step * 1e-3, ("fp8", "cont"): mse * 1e-3,
+                 ("fp32", "sign"): ms32 * 1e-3, ("fp32", "cont"): ms32 * 1e-3,
+                 ("fix16", "cont"): ms16 * 1e-3}
+        plan = [("fp8", g8, True), ("fp8", g8, False), ("fp32", g32, True), ("fp32", g32, False),
+                ("fix16", g16, False)]
+        for form, g, sign in plan:
+            vs = [("dsb", 0.0)] + [("gdsb", a) for a in A_SWEEP] if sign else \
+                 [("bsb", 0.0)] + [("gbsb", a) for a in A_SWEEP]
+            for variant, A in vs:
                 g.run(variant, A=A, dt=DT, replicas=R, steps=M, seed=5000)
-                runs.append((form, variant, A, g.energy()))
-        for variant, A in [("dsb", 0.0)] + [("gdsb", a) for a in A_SWEEP]:
-            g8.run(variant, A=A, dt=DT, replicas=R, steps=M, seed=5000)
-            runs.append(("fp8", variant, A, g8.energy()))
+                runs.append((form, "sign" if sign else "cont", variant, A, g.energy()))
         e_star = min(float(E.min()) for *_, E in runs)
         table = []
-        for form, variant, A, E in runs:
-            p = float(np.mean(E == e_star))
-            p_run = 1.0 - (1.0 - p) ** R
-            table.append({"form": form, "variant": variant, "A": A, "p_hat": p,
-                          "dp_hat": math.sqrt(max(p - p * p, 0.0) / R), "best": float(E.min()),
-                          "mean": float(E.mean()),
-                          "tts99_s": _finite(tts99(t_com[form], p_run))})
-        best_row = {f: max((t for t in table if t["form"] == f and t["variant"] == "gbsb"), key=lambda t: t["p_hat"])
-                    for f in ("fp8", "fp32", "fix16")}
+        for form, kind, variant, A, E in runs:
+            d = stats.batch_tts(t_com[(form, kind)], int(np.sum(E == e_star)), R)
+            table.append({"form": form, "variant": variant, "A": A, "p_hat": d["p_hat"], "dp_hat": d["dp_hat"],
+                          "best": float(E.min()), "mean": float(E.mean()), "t_com_s": t_com[(form, kind)],
+                          "tts99_s": _finite(d["tts99_s"]), "dtts99_s": _finite(d["dtts99_s"])})
+        # the sign-product rows of the FP8 and FP32 forms: equal energies replica by replica
+        sign8 = {(v, A): E for f, k, v, A, E in runs if f == "fp8" and k == "sign"}
+        sign32 = {(v, A): E for f, k, v, A, E in runs if f == "fp32" and k == "sign"}
+        fp8_vs_fp32 = [{"variant": v, "A": A, "energies_identical": bool(np.array_equal(sign8[(v, A)], sign32[(v, A)])),
+                        "p_hat": float(np.mean(sign8[(v, A)] == e_star)),
+                        "tts99_fp8_s": _finite(stats.batch_tts(t_com[("fp8", "sign")],
+                                                               int(np.sum(sign8[(v, A)] == e_star)), R)["tts99_s"]),
+                        "tts99_fp32_s": _finite(stats.batch_tts(t_com[("fp32", "sign")],
+                                                                int(np.sum(sign32[(v, A)] == e_star)), R)["tts99_s"])}
+                       for (v, A) in sign8]
+        best_row = {}
+        for key, (f, v) in {"fp8_gdsb": ("fp8", "gdsb"), "fp32_gdsb": ("fp32", "gdsb"), "fp8_e4m3_gbsb": ("fp8", "gbsb"),
+                            "fp32_gbsb": ("fp32", "gbsb"), "fix16_gbsb": ("fix16", "gbsb")}.items():
+            best_row[key] = max((t for t in table if t["form"] == f and t["variant"] == v), key=lambda t: t["p_hat"])
         out["success"] = {"e_star": e_star, "cut_star": -0.5 * (float(np.triu(J, 1).sum()) + e_star),
-                          "tts_semantics": "T_com = one launch of all replicas; P_S of the batch = 1-(1-p_hat)^R",
-                          "best_gbsb": best_row, "table": table}
-        out["tts99_s"] = best_row["fp8"]["tts99_s"]
-        out["success"]["tts_vs_replicas"] = tts_vs_replicas(g8, [best_row["fp8"], table[0]])
+                          "tts_semantics": "T_com = one launch of all replicas; P_S of the batch = 1-(1-p_hat)^R; "
+                                           "dTTS = TTS dp_hat / ((1 - p_hat)|ln(1 - p_hat)|)",
+                          "best": best_row, "fp8_vs_fp32_sign_product": fp8_vs_fp32, "table": table}
+        out["tts99_s"] = best_row["fp8_gdsb"]["tts99_s"]
+        out["dtts99_s"] = best_row["fp8_gdsb"]["dtts99_s"]
+        out["success"]["tts_vs_replicas"] = tts_vs_replicas(g8, [best_row["fp8_gdsb"],
+                                                                 next(t for t in table if t["variant"] == "dsb")])
+    g8.close()
+    g32.close()
+    g16.close()
     if not args.no_chaos:
         out["chaos"] = chaos_sweeps(J, c)
     if not args.no_batch:
@@ -527,8 +695,7 @@ def main():
     ceil = gsb.gsb_device_ceilings()
     ceil["headline_frac_of_measured_fp4xfp8"] = achieved * 1e12 / ceil["mfma_fp4xfp8_flops"]
     out["ceilings"] = ceil
-    # L2 reads of the step kernel (operand fragments, read by each of the four product
-    # waves of a CU) against this device's measured streaming L2 read rate
+    # L2 reads of the step kernel against this device's measured L2 read rate
     l2 = load_l2_read("k_steps_ws_fp8_n2000_r1024_counters.json")
     if l2 is not None:
         rate = l2 / (k_ms * 1e-3)
@@ -536,8 +703,13 @@ def main():
                                       "measured_peak_Bps": ceil["read_l2_2MiB_Bps"],
                                       "frac": rate / ceil["read_l2_2MiB_Bps"]}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(J.astype(np.float64), c)
-    print(json.dumps(out))
+        out["cpu_baseline"] = cpu_baseline(J, c)
+        out["cpu_baseline"]["config1_fp64"] = config1_fp64()
+        out["cpu_baseline"]["errors_vs_fp64"] = errors_vs_fp64(J.astype(np.float64), c)
+    # nothing of the library or of torch's device memory is left for the exit handlers
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -93,6 +93,8 @@ def _load():
     lib.orc_delta.argtypes = [vp, vp, i32]
     lib.orc_num_threads.restype = i32
     lib.orc_num_threads.argtypes = []
+    lib.orc_set_num_threads.restype = None
+    lib.orc_set_num_threads.argtypes = [i32]
     lib.orc_init_pairs.restype = None
     lib.orc_init_pairs.argtypes = [i32, i32, u64, vp, vp]
     lib.orc_tangent_run_f64.restype = i32
@@ -110,6 +112,11 @@ def _p(a: np.ndarray):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    """Threads of the loops over replicas (timing only; results do not depend on it)."""
+    _load().orc_set_num_threads(int(t))
 
 
 # ---- generator (SplitMix64, counter form) -----------------------------------------------

@@ -553,6 +553,16 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Threads the parallel loops over replicas use from here on (timing only; the results do
+ * not depend on it: each replica is computed by one thread in a fixed order). */
+void orc_set_num_threads(int t) {
+#ifdef _OPENMP
+  if (t > 0) omp_set_num_threads(t);
+#else
+  (void)t;
+#endif
+}
+
 /* Batch forms of the format conversions (for tests over many values). */
 void orc_e4m3_round_array(const double* in, double* out, int64_t count) {
   for (int64_t k = 0; k < count; ++k) out[k] = orc_e4m3_round(in[k]);

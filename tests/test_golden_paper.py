@@ -1,6 +1,6 @@
 """Checks against the values the paper prints (tests/golden/paper_values.json, each entry
 with its citation).  CPU only: the oracle, the library's host-side eigenvalue code and the
-benchmark's TTS helper."""
+host statistics module."""
 import json
 import math
 import os
@@ -67,14 +67,14 @@ def test_random_pm1_matrix_step_size():
 
 
 def test_tts_definition():
-    import bench
+    from paper_2508_17655_amd import stats
     p99 = PAPER["tts_target"]["value"]
-    assert bench.tts99(3.0, 0.995) == 3.0          # P_S above the target: one run
-    assert bench.tts99(3.0, 1.0) == 3.0
-    assert bench.tts99(3.0, 0.0) == math.inf
+    assert stats.tts99(3.0, 0.995) == 3.0          # P_S above the target: one run
+    assert stats.tts99(3.0, 1.0) == 3.0
+    assert stats.tts99(3.0, 0.0) == math.inf
     # P_S = 0.5: ln(0.01)/ln(0.5) = 6.644 runs
-    assert bench.tts99(1.0, 0.5) == pytest.approx(6.6439, abs=1e-4)
+    assert stats.tts99(1.0, 0.5) == pytest.approx(6.6439, abs=1e-4)
     # P_S = 1 - (1 - 0.99)^(1/k) needs exactly k runs: 1 - (1 - P_S)^k = 0.99
     for k in (2, 5, 40):
         ps = 1 - (1 - p99) ** (1 / k)
-        assert bench.tts99(1.0, ps) == pytest.approx(k, rel=1e-12)
+        assert stats.tts99(1.0, ps) == pytest.approx(k, rel=1e-12)
