@@ -169,6 +169,31 @@ gsb_status gsb_step(gsb_ctx* ctx, int32_t count);
 gsb_status gsb_run(gsb_ctx* ctx, int32_t variant, int32_t schedule, double control_strength,
                    double dt, int32_t replicas, int32_t steps, uint64_t seed);
 
+/* gsb_run without device allocation, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid allocation).  It
+ * computes the same bits as gsb_run followed by gsb_energy for the same context and
+ * arguments, but every device buffer of the run (the copies of J, the state, the operand
+ * buffers, the barrier words, the energy sums and the schedule table) lives in one array
+ * of 64 MiB per device that the library holds from its load onto a device until the
+ * process ends; no hipMalloc or hipFree is called.  The context's own workspace (bound or
+ * allocated) is neither used nor changed.
+ *   x        : device, replicas * n_dyn binary32, replica-major (n_dyn = GSB_OPT_N_DYN):
+ *              x at t_M.
+ *   energies : device, replicas doubles: the eq. (1) energies of sgn(x) at t_M.
+ *   other arguments as gsb_run.
+ * Limit: the run must fit in the array (what gsb_workspace_size reports for the same
+ * replicas and steps, at most 64 MiB; for example n = 2000 with 1024 replicas in the FP8
+ * precision); a larger run fails with EINVAL before any device work.
+ * All calls on one device share that device's array, which keeps the last call's contents
+ * (a later call by the same context reuses its J there, any other call overwrites it):
+ * calls that overlap in time on one device race and give undefined results, so serialise
+ * them (one host thread, one stream at a time).  Enqueued on the context's stream; then
+ * synchronises it and checks the barrier status.  Afterwards the context has no current run
+ * (ESTATE for gsb_step, gsb_energy, gsb_state, ...).
+ * Errors: EINVAL, EUNSUPPORTED, EDEVICE. */
+gsb_status gsb_run_noalloc(gsb_ctx* ctx, int32_t variant, int32_t schedule, double control_strength, double dt,
+                           int32_t replicas, int32_t steps, uint64_t seed, float* x, double* energies);
+
 /* Ising energies, eq. (1), of s = sgn(x) (sgn(0) = +1) at the current step, one per
  * replica.  energies: host, `replicas` doubles.  Exact for integer J; binary64
  * accumulation otherwise.  Synchronises the stream.  Errors: ESTATE, EINVAL, EDEVICE. */

@@ -6,9 +6,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -169,6 +171,7 @@ void gsb::extreme_eigenvalues(const float* J, int n, double* lmax, double* lmin)
 
 struct gsb_ctx {
   // instance
+  uint64_t uid = 0;  // unique per context of the process (never reused)
   int n_user = 0, n = 0, np = 0, anc = -1;
   std::vector<float> J;  // n x n, row-major (with the ancilla row/column if any)
   bool pm1 = false;
@@ -400,6 +403,8 @@ gsb_status gsb_create(const float* J, const float* h, int32_t n, gsb_ctx** out) 
   }
   gsb_ctx* c = new (std::nothrow) gsb_ctx;
   if (!c) return fail(GSB_ENOMEM, "host allocation failed");
+  static std::atomic<uint64_t> next_uid{1};
+  c->uid = next_uid.fetch_add(1);
   c->n_user = n;
   c->n = field ? n + 1 : n;
   c->anc = field ? n : -1;
@@ -553,7 +558,8 @@ namespace {
 // Point the context's buffers into the workspace laid out by `L`, upload and encode J
 // for product form `form` if the workspace does not hold it yet, and write the schedule
 // table r_m = 1 / (M - m) (eqs. (6), (7)), binary64 rounded once.
-gsb_status carve_and_prepare(gsb_ctx* c, const Layout& L, int kind, int form, int schedule, int steps) {
+gsb_status carve_and_prepare(gsb_ctx* c, const Layout& L, int kind, int form, int schedule, int steps,
+                              bool device_rtab = false) {
   uint8_t* b = c->ws;
   const bool j32_moved = reinterpret_cast<float*>(b + L.j32) != c->j32;
   c->j32 = reinterpret_cast<float*>(b + L.j32);
@@ -590,11 +596,15 @@ gsb_status carve_and_prepare(gsb_ctx* c, const Layout& L, int kind, int form, in
     HIP_TRY(launch_encode_j(form, j_fp4, c->j32, c->np, c->jf, c->stream), "encode J");
     c->jf_form = jcode;
   }
-  c->rtab_host.assign(steps, 0.0f);
-  if (schedule == GSB_SCHED_LINEAR)
-    for (int m = 0; m < steps; ++m) c->rtab_host[m] = (float)(1.0 / (double)(steps - m));
-  HIP_TRY(hipMemcpyAsync(c->rtab, c->rtab_host.data(), (size_t)steps * 4, hipMemcpyHostToDevice, c->stream),
-          "upload schedule");
+  if (device_rtab) {
+    HIP_TRY(launch_rtab(c->rtab, steps, schedule == GSB_SCHED_LINEAR, c->stream), "schedule table");
+  } else {
+    c->rtab_host.assign(steps, 0.0f);
+    if (schedule == GSB_SCHED_LINEAR)
+      for (int m = 0; m < steps; ++m) c->rtab_host[m] = (float)(1.0 / (double)(steps - m));
+    HIP_TRY(hipMemcpyAsync(c->rtab, c->rtab_host.data(), (size_t)steps * 4, hipMemcpyHostToDevice, c->stream),
+            "upload schedule");
+  }
   HIP_TRY(launch_fill_u32(c->status, 64, 0u, c->stream), "clear status");
   return GSB_OK;
 }
@@ -649,9 +659,11 @@ gsb_status launch_chunks(gsb_ctx* c, int form, int cols, bool discrete, float A,
 
 }  // namespace
 
-gsb_status gsb_init(gsb_ctx* c, int32_t variant, int32_t schedule, double A, double dt, int32_t replicas,
-                    int32_t steps, uint64_t seed) {
-  g_err.clear();
+namespace {
+
+// Arguments of a run (gsb_init, gsb_run_noalloc); sets c = 1/lambda_max (App. A) if unset.
+gsb_status check_run_args(gsb_ctx* c, int32_t variant, int32_t schedule, double A, double dt, int32_t replicas,
+                          int32_t steps) {
   if (!c) return fail(GSB_EINVAL, "ctx is NULL");
   if (variant < GSB_BSB || variant > GSB_GDSB) return fail(GSB_EINVAL, "unknown variant");
   if (schedule < GSB_SCHED_LINEAR || schedule > GSB_SCHED_CONSTANT) return fail(GSB_EINVAL, "unknown schedule");
@@ -665,6 +677,16 @@ gsb_status gsb_init(gsb_ctx* c, int32_t variant, int32_t schedule, double A, dou
     ensure_eig(c);
     c->c = c->lmax > 0 ? 1.0 / c->lmax : 1.0;  // App. A: c = 1 / lambda_max
   }
+  return GSB_OK;
+}
+
+}  // namespace
+
+gsb_status gsb_init(gsb_ctx* c, int32_t variant, int32_t schedule, double A, double dt, int32_t replicas,
+                    int32_t steps, uint64_t seed) {
+  g_err.clear();
+  gsb_status s0 = check_run_args(c, variant, schedule, A, dt, replicas, steps);
+  if (s0 != GSB_OK) return s0;
   Layout L;
   int kind;
   gsb_status s = plan(c, replicas, steps, &L, &kind);
@@ -722,6 +744,124 @@ gsb_status gsb_run(gsb_ctx* c, int32_t variant, int32_t schedule, double A, doub
   s = gsb_step(c, steps);
   if (s != GSB_OK) return s;
   return compute_energy(c);
+}
+
+// ---- allocation-free run ---------------------------------------------------------------
+// Every device buffer of a gsb_run_noalloc call lives in `scratch`: one copy per device,
+// which the library holds from its load onto that device until the process ends.  Host
+// code never passes the array's name as an address: each device's copy is located once,
+// at the entry point's first call on that device (with that device current), and that
+// address is what the kernels and copies receive.
+namespace {
+
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+constexpr int kNoAllocMaxDevices = 64;
+
+struct ScratchSlot {
+  uint8_t* ptr = nullptr;  // this device's copy of `scratch`
+  uint64_t j_owner = 0;    // uid of the context whose J the array holds (0: none)
+  int j_form = -1;         // jf_form code of that context's encoded J there
+};
+std::mutex g_scratch_mu;
+ScratchSlot g_scratch[kNoAllocMaxDevices];
+
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+gsb_status gsb_run_noalloc(gsb_ctx* c, int32_t variant, int32_t schedule, double A, double dt, int32_t replicas,
+                           int32_t steps, uint64_t seed, float* x, double* energies) {
+  g_err.clear();
+  gsb_status s = check_run_args(c, variant, schedule, A, dt, replicas, steps);
+  if (s != GSB_OK) return s;
+  if (!x || !energies) return fail(GSB_EINVAL, "x and energies must be device pointers");
+  if (((uintptr_t)x & 3u) != 0 || ((uintptr_t)energies & 7u) != 0)
+    return fail(GSB_EINVAL, "x must be 4-byte and energies 8-byte aligned");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev), "current device");
+  if (dev < 0 || dev >= kNoAllocMaxDevices)
+    return fail(GSB_EUNSUPPORTED, "device index beyond the " + std::to_string(kNoAllocMaxDevices) +
+                                      " the allocation-free entry point tracks");
+  uint8_t* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev].ptr) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "locating the scratch array");
+      g_scratch[dev].ptr = static_cast<uint8_t*>(p);
+    }
+    base = g_scratch[dev].ptr;
+  }
+  Layout L;
+  int kind;
+  s = plan(c, replicas, steps, &L, &kind);
+  if (s != GSB_OK) return s;
+  if (L.total > kNoAllocBytes)
+    return fail(GSB_EINVAL, "the run needs " + std::to_string(L.total) + " bytes of device memory; an allocation-free "
+                            "run has " + std::to_string(kNoAllocBytes) + " (use fewer replicas or steps, or gsb_run)");
+  // The context's own workspace stays as it is; for this call its buffers point into the
+  // array.  J is uploaded and encoded unless this context's J is still there.
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    const bool mine = g_scratch[dev].j_owner == c->uid;
+    c->j32_ready = mine;
+    c->jf_form = mine ? g_scratch[dev].j_form : -1;
+    g_scratch[dev].j_owner = 0;  // rewritten below
+  }
+  c->ws = base;
+  c->ws_bytes = kNoAllocBytes;
+  c->j32 = reinterpret_cast<float*>(base + L.j32);
+  c->jf = base + L.jf;
+  c->inited = false;
+  auto detach = [&](gsb_status st) {
+    {
+      std::lock_guard<std::mutex> lk(g_scratch_mu);
+      if (st == GSB_OK && c->j32_ready) {
+        g_scratch[dev].j_owner = c->uid;
+        g_scratch[dev].j_form = c->jf_form;
+      }
+    }
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    c->j32_ready = false;
+    c->jf_form = -1;
+    c->inited = false;
+    c->energy_valid = false;
+    c->timed = false;
+    return st;
+  };
+#define NOALLOC_TRY(expr, what)                              \
+  do {                                                       \
+    hipError_t e_ = (expr);                                  \
+    if (e_ != hipSuccess) return detach(hip_fail(e_, what)); \
+  } while (0)
+  const int form = form_of(c->precision);
+  const int rp = (replicas + kRepPad - 1) / kRepPad * kRepPad;
+  s = carve_and_prepare(c, L, kind, form, schedule, steps, /*device_rtab=*/true);
+  if (s != GSB_OK) return detach(s);
+  c->variant = variant;
+  c->schedule = schedule;
+  c->A = (variant == GSB_GBSB || variant == GSB_GDSB) ? A : 0.0;
+  c->dt = dt;
+  c->R = replicas;
+  c->rp = rp;
+  c->M = steps;
+  c->m = 0;
+  c->seed = seed;
+  c->energy_valid = false;
+  NOALLOC_TRY(launch_init_state(c->n, c->np, rp, seed, c->init_mode, c->X, c->Y, c->P, c->stream), "init state");
+  s = launch_chunks(c, form, rp, variant == GSB_DSB || variant == GSB_GDSB, (float)c->A, nullptr, 0, steps, false);
+  if (s != GSB_OK) return detach(s);
+  s = compute_energy(c);
+  if (s != GSB_OK) return detach(s);
+  NOALLOC_TRY(hipMemcpy2DAsync(x, (size_t)c->n * 4, c->X, (size_t)c->np * 4, (size_t)c->n * 4, replicas,
+                               hipMemcpyDeviceToDevice, c->stream),
+              "copy x");
+  NOALLOC_TRY(hipMemcpyAsync(energies, c->E, (size_t)replicas * 8, hipMemcpyDeviceToDevice, c->stream),
+              "copy energies");
+#undef NOALLOC_TRY
+  return detach(check_status_word(c));
 }
 
 gsb_status gsb_energy(gsb_ctx* c, double* energies) {

@@ -40,6 +40,8 @@ struct BatchArgs {
 // ---- launchers (all asynchronous on `stream`) ----
 hipError_t launch_fill_u32(unsigned* p, size_t count, unsigned v, hipStream_t stream);
 hipError_t launch_encode_j(int form, bool fp4, const float* j32, int np, void* jf, hipStream_t stream);
+// r_m = fl32(1 / (M - m)) for m < steps (linear schedule), else 0, computed on the device.
+hipError_t launch_rtab(float* rtab, int steps, bool linear, hipStream_t stream);
 hipError_t launch_encode_operand(int form, bool discrete, const float* x, size_t count, void* out,
                                  hipStream_t stream);
 hipError_t launch_init_state(int n, int np, int rp, uint64_t seed, int mode, float* x, float* y,

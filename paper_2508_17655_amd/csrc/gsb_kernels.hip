@@ -822,6 +822,14 @@ __global__ void k_fill_u32(unsigned* p, size_t count, unsigned v) {
     p[t] = v;
 }
 
+// Schedule table r_m = 1 / (M - m) of eqs. (6), (7), the binary64 quotient rounded to
+// binary32 once (the same bits as the host table: both divisions are correctly rounded);
+// all zero for the constant schedule.
+__global__ void k_rtab(float* rtab, int steps, int linear) {
+  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < steps; m += gridDim.x * blockDim.x)
+    rtab[m] = linear ? (float)(1.0 / (double)(steps - m)) : 0.0f;
+}
+
 // J (row-major np x np binary32, zero padded) -> fragment-major layout of `FORM`.
 template <int FORM>
 __global__ void k_encode_j(const float* j32, int np, uint8_t* jf) {
@@ -1323,6 +1331,11 @@ const void* steps_kernel_for(int form, int kind, int np, bool discrete) {
 // ---------------------------------------------------------------------------------------
 hipError_t launch_fill_u32(unsigned* p, size_t count, unsigned v, hipStream_t stream) {
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(count, 256)), dim3(256), 0, stream, p, count, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_rtab(float* rtab, int steps, bool linear, hipStream_t stream) {
+  hipLaunchKernelGGL(k_rtab, dim3(grid_for((size_t)steps, 256)), dim3(256), 0, stream, rtab, steps, linear ? 1 : 0);
   return hipGetLastError();
 }
 

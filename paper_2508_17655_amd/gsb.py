@@ -39,7 +39,7 @@ STATUS_NAMES = {0: "GSB_OK", -1: "GSB_EINVAL", -2: "GSB_ENOTSYM", -3: "GSB_EDIAG
 
 # Every symbol include/gsb.h declares.
 SYMBOLS = ("gsb_create", "gsb_destroy", "gsb_set", "gsb_get", "gsb_set_stream", "gsb_workspace_size",
-           "gsb_bind_workspace", "gsb_init", "gsb_step", "gsb_run", "gsb_energy", "gsb_best", "gsb_spins",
+           "gsb_bind_workspace", "gsb_init", "gsb_step", "gsb_run", "gsb_run_noalloc", "gsb_energy", "gsb_best", "gsb_spins",
            "gsb_state", "gsb_set_state", "gsb_delta", "gsb_lle_workspace_size", "gsb_lle", "gsb_vjp", "gsb_last_step_ms",
            "gsb_batch_create", "gsb_batch_destroy", "gsb_batch_set_stream", "gsb_batch_workspace_size",
            "gsb_batch_bind_workspace", "gsb_batch_set_coupling", "gsb_batch_set", "gsb_batch_get", "gsb_batch_autotune",
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH):
         "gsb_init": (i32, [vp, i32, i32, dbl, dbl, i32, i32, u64]),
         "gsb_step": (i32, [vp, i32]),
         "gsb_run": (i32, [vp, i32, i32, dbl, dbl, i32, i32, u64]),
+        "gsb_run_noalloc": (i32, [vp, i32, i32, dbl, dbl, i32, i32, u64, vp, vp]),
         "gsb_energy": (i32, [vp, vp]),
         "gsb_best": (i32, [vp, vp, ctypes.POINTER(dbl), ctypes.POINTER(i32)]),
         "gsb_spins": (i32, [vp, vp]),
@@ -191,6 +192,13 @@ def gsb_run(ctx, variant: int, schedule: int, control_strength: float, dt: float
             seed: int) -> None:
     _check(load_library().gsb_run(ctx, variant, schedule, control_strength, dt, replicas, steps,
                                   seed & (2**64 - 1)), "gsb_run")
+
+
+def gsb_run_noalloc(ctx, variant: int, schedule: int, control_strength: float, dt: float, replicas: int,
+                    steps: int, seed: int, x_ptr: int, energies_ptr: int) -> None:
+    """x_ptr, energies_ptr: device addresses (replicas * n_dyn binary32, replicas doubles)."""
+    _check(load_library().gsb_run_noalloc(ctx, variant, schedule, control_strength, dt, replicas, steps,
+                                          seed & (2**64 - 1), x_ptr, energies_ptr), "gsb_run_noalloc")
 
 
 def gsb_energy(ctx) -> np.ndarray:
