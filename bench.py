@@ -278,45 +278,60 @@ def cpu_baseline(J, c, target_s: float = 12.0):
 
 
 def chaos_sweeps(J, c):
-    """Edge-of-chaos diagnostics on the same instance (binary32 form, continuous product):
-    LLE estimates for 16 control strengths log-spaced over two decades x 64 replicas in one
-    batched tangent run of 500 steps, and the paper's delta(t_M) (eq. (8)) of 64 trajectory
-    pairs per A of the success sweep after 2000 steps (Sec. IV)."""
+    """Edge-of-chaos diagnostics on the same instance (binary32 form, continuous product),
+    Sec. IV.  The sweep: 16 control strengths log-spaced over two decades x 64 replicas,
+    T = 500 steps, dt = 1.25, in one batched tangent run per estimate -- the largest-
+    Lyapunov-exponent estimate over the whole run, and over its last fifth (the window
+    after the bifurcation, where the pump's own exponential growth through it no longer
+    counts) -- and, on the same grid and schedule, the paper's delta(t_M) (eq. (8)) of 64
+    trajectory pairs per A.  Beside it, delta(t_M) over the success sweep's schedule
+    (M = 2000 steps) at its control strengths."""
     import numpy as np
     import torch
 
     from paper_2508_17655_amd import gsb
 
-    a_vals = [10.0 ** (-2.0 + 2.0 * k / 15.0) for k in range(16)]
-    per = 64
-    A = np.repeat(np.array(a_vals), per)
-    T, renorm = 500, 10
+    grid = [10.0 ** (-2.0 + 2.0 * k / 15.0) for k in range(16)]
+    per, T, renorm = 64, 500, 10
+    m_w = (4 * T) // 5
+    A = np.repeat(np.array(grid), per)
     g = gsb.GSB(J, precision="fp32", c=c)
     g.lle("gbsb", A=A[:per], dt=DT, replicas=per, steps=20, seed=1, tangent_seed=2, renorm_every=renorm)  # warm-up
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lle = g.lle("gbsb", A=A, dt=DT, replicas=A.size, steps=T, seed=11, tangent_seed=12, renorm_every=renorm)
-    wall = time.perf_counter() - t0
-    dev_ms = g.last_step_ms()
+    est = {}
+    for name, w in (("whole", 0), ("window", m_w)):
+        t0 = time.perf_counter()
+        lle = g.lle("gbsb", A=A, dt=DT, replicas=A.size, steps=T, seed=11, tangent_seed=12, renorm_every=renorm,
+                    window_from=w).reshape(len(grid), per)
+        fin = np.where(np.isfinite(lle), lle, np.nan)
+        with np.errstate(all="ignore"):
+            mean, std = np.nanmean(fin, axis=1), np.nanstd(fin, axis=1)
+        est[name] = {"from_step": w, "mean": [_finite(float(v)) for v in mean],
+                     "std": [_finite(float(v)) for v in std],
+                     "vanished": [int(v) for v in np.sum(~np.isfinite(lle), axis=1)],
+                     "ms": (time.perf_counter() - t0) * 1e3, "device_ms": g.last_step_ms()}
     g.close()
-    lle = lle.reshape(16, per)
-    fin = np.where(np.isfinite(lle), lle, np.nan)
-    res = {"lle": {"A": a_vals, "mean": [_finite(float(v)) for v in np.nanmean(fin, axis=1)],
-                   "std": [_finite(float(v)) for v in np.nanstd(fin, axis=1)],
-                   "vanished": [int(v) for v in np.sum(~np.isfinite(lle), axis=1)],
-                   "replicas": int(A.size), "steps": T, "renorm_every": renorm, "ms": wall * 1e3,
-                   "device_ms": dev_ms, "n": N, "form": "fp32 (primal and tangent)"}}
     pairs = 64
     gp = gsb.GSB(J, precision="fp32", c=c, init_mode=gsb.GSB_INIT_PAIRS)
-    dmean = []
-    t0 = time.perf_counter()
-    for a in [0.0] + A_SWEEP:
-        gp.run("gbsb", A=a, dt=DT, replicas=2 * pairs, steps=M, seed=21)
-        dmean.append(float(np.mean(gp.delta())))
-    res["delta"] = {"A": [0.0] + A_SWEEP, "mean": dmean, "pairs": pairs, "steps": M, "ms": (time.perf_counter() - t0) * 1e3,
-                    "form": "fp32", "chaos_level": 1.0 / math.sqrt(2.0)}
+
+    def delta_at(a_vals, steps):
+        t0 = time.perf_counter()
+        d = []
+        for a in a_vals:
+            gp.run("gbsb", A=a, dt=DT, replicas=2 * pairs, steps=steps, seed=21)
+            d.append(float(np.mean(gp.delta())))
+        return d, (time.perf_counter() - t0) * 1e3
+
+    d_grid, ms_grid = delta_at(grid, T)
+    d_sweep, ms_sweep = delta_at([0.0] + A_SWEEP, M)
     gp.close()
-    return res
+    return {"A": grid, "n": N, "steps": T, "dt": DT, "form": "fp32 (primal and tangent)",
+            "lle": {"replicas_per_A": per, "renorm_every": renorm, "whole_run": est["whole"],
+                    "post_bifurcation": est["window"],
+                    "vanished": "replicas whose every tangent component reached a wall (estimate -inf)"},
+            "delta": {"mean": d_grid, "pairs": pairs, "ms": ms_grid, "chaos_level": 1.0 / math.sqrt(2.0)},
+            "delta_success_schedule": {"A": [0.0] + A_SWEEP, "steps": M, "mean": d_sweep, "pairs": pairs,
+                                       "ms": ms_sweep}}
 
 
 BATCH_COUNT, BATCH_R, BATCH_M, BATCH_A = 256, 128, 1000, 0.2
@@ -462,6 +477,14 @@ def dt_study(J, c):
     return {"A": A, "form": "fix16", "replicas": R, "pairs": 64, "e_star": e_star, "s": wall, "table": rows}
 
 
+_T0 = time.perf_counter()
+
+
+def _say(msg):
+    """One progress line on stderr per finished leg (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -576,6 +599,7 @@ def main():
         torch.cuda.synchronize()
         return 1000 * (time.perf_counter() - t1) / reps, float(np.mean(ks))
 
+    _say(f"headline timed: {ms_per_step:.3f} ms per launch")
     # ---- the FP32 form of the same run: the same bits, on binary32 MFMA ----
     g32 = gsb.GSB(J, precision="fp32", c=c)
     ms32, k32 = timed(g32, HEAD_VARIANT, 3000)
@@ -586,6 +610,7 @@ def main():
                  "ms_per_run": ms32, "kernel_ms": k32, "mfma_frac": flop / (k32 * 1e-3) / FP32_MFMA_PEAK,
                  "state_bit_identical_to_fp8": same_bits, "fp8_speedup": ms32 / ms_per_step}
 
+    _say("fp32 form done")
     # ---- GbSB (continuous product) in the 16-bit fixed-point form: the paper's JX precision,
     # exact (two int8 passes, exact int32 sums) ----
     g16 = gsb.GSB(J, precision="fix16", c=c)
@@ -596,6 +621,7 @@ def main():
                                "unit": "TOP/s", "frac": flop / (k16 * 1e-3) / INT8_PEAK,
                                "frac_executed": 2 * flop / (k16 * 1e-3) / INT8_PEAK,
                                "note": "frac counts the algorithmic 2 N^2 R M once; the form executes two int8 passes"}}
+    _say("fix16 form done")
     # ---- GbSB with the operand rounded to E4M3 (narrower than the paper's JX) ----
     mse, kse = timed(g8, "gbsb", 3200)
     e4m3_form = {"variant": "gbsb", "value": R * N * M / (mse * 1e-3), "unit": "replica-spin-steps/s",
@@ -650,6 +676,7 @@ def main():
             for variant, A in vs:
                 g.run(variant, A=A, dt=DT, replicas=R, steps=M, seed=5000)
                 runs.append((form, "sign" if sign else "cont", variant, A, g.energy()))
+            _say(f"success rows: {form} {'sign' if sign else 'continuous'} product")
         e_star = min(float(E.min()) for *_, E in runs)
         table = []
         for form, kind, variant, A, E in runs:
@@ -684,12 +711,16 @@ def main():
     g16.close()
     if not args.no_chaos:
         out["chaos"] = chaos_sweeps(J, c)
+        _say("chaos sweeps done")
     if not args.no_batch:
         out["batched"] = batched_uneven()
+        _say("batched workload done")
     if not args.no_dt:
         out["dt_study"] = dt_study(J, c)
+        _say("dt study done")
     if not args.no_precision:
         out["precision"] = precision_forms(J, c)
+        _say("precision forms done")
     # this device's measured ceilings (MFMA rates, streaming bandwidths, clock), beside the
     # published peaks the roofline fractions use
     ceil = gsb.gsb_device_ceilings()
@@ -704,6 +735,7 @@ def main():
                                       "frac": rate / ceil["read_l2_2MiB_Bps"]}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(J, c)
+        _say("cpu baseline done")
         out["cpu_baseline"]["config1_fp64"] = config1_fp64()
         out["cpu_baseline"]["errors_vs_fp64"] = errors_vs_fp64(J.astype(np.float64), c)
     # nothing of the library or of torch's device memory is left for the exit handlers

@@ -111,7 +111,13 @@ typedef enum {
                              exchange the operand through its L2; 0: no padding, a group's
                              workgroups may sit on several XCDs and every step then goes
                              through a group counter with device-scope fences (slower; the
-                             results are the same bits).  Takes effect at the next launch. */
+                             results are the same bits).  Takes effect at the next launch. */,
+  GSB_OPT_LLE_FROM = 12   /* first step m_w whose tangent growth gsb_lle counts (default 0):
+                             the estimate becomes ln(|v(t_M)| / |v(t_w)|) / ((M - m_w) dt),
+                             with the tangent renormalised to unit norm at t_w, so that the
+                             window after the bifurcation (Sec. IV) can be measured apart
+                             from the pump's growth through it.  Integer >= 0; gsb_lle
+                             rejects a value >= its `steps`. */
 } gsb_option;
 
 /* Create a context for the instance (J, h).
@@ -219,6 +225,18 @@ gsb_status gsb_state(gsb_ctx* ctx, float* x, float* y, float* p, int32_t* m);
  * Errors: ESTATE, EINVAL, ENONFINITE, EDEVICE. */
 gsb_status gsb_set_state(gsb_ctx* ctx, const float* x, const float* y, const float* p, int32_t m);
 
+/* gsb_state and gsb_set_state with the arrays in device memory (e.g. a framework's tensors
+ * on the context's device), so that a checkpointed trajectory (the differentiation path)
+ * keeps its state on the device.  Layout as for the host versions: replicas * n_dyn
+ * binary32 each, replica-major, caller-owned.  The copies run on the context's stream
+ * (gsb_set_stream); order the caller's own work on the arrays with it.  gsb_state_device
+ * synchronises and checks the barrier status like gsb_state.  gsb_set_state_device makes
+ * gsb_set_state's checks in a kernel (non-finite entries: ENONFINITE; |x| > 1: EINVAL,
+ * the state left as it was) and synchronises.
+ * Errors: ESTATE, EINVAL, ENONFINITE, EDEVICE. */
+gsb_status gsb_state_device(gsb_ctx* ctx, float* x, float* y, float* p, int32_t* m);
+gsb_status gsb_set_state_device(gsb_ctx* ctx, const float* x, const float* y, const float* p, int32_t m);
+
 /* Normalised distance of the trajectory pairs, eq. (8) (Sec. IV), at the current step:
  * delta_k = sqrt(sum_i (x_i(2k) - x_i(2k+1))^2 / (4 n)) over the n spins of the instance
  * (a field ancilla excluded), for k < replicas/2.  Meaningful for runs started with
@@ -243,8 +261,9 @@ gsb_status gsb_delta(gsb_ctx* ctx, double* out);
  *                      over (dx, dy, dp).
  *   renorm_every     : steps between rescalings of the tangent to unit norm (>= 1); the
  *                      logarithms of the norms are summed in binary64.
- *   lle              : host, `replicas` doubles: ln(|v(t_M)| / |v(0)|) / (M dt), or -inf
- *                      when every component of the tangent reached a wall.
+ *   lle              : host, `replicas` doubles: ln(|v(t_M)| / |v(t_w)|) / ((M - m_w) dt)
+ *                      with m_w = GSB_OPT_LLE_FROM (0 by default), or -inf when every
+ *                      component of the tangent reached a wall.
  *   state_out        : host, 6 * replicas * n_dyn floats or NULL: x, y, p, dx, dy, dp at
  *                      t_M (the tangent at unit norm), each replica-major.
  * Uses the context's workspace; afterwards the context has no current run (ESTATE for
@@ -269,6 +288,11 @@ gsb_status gsb_lle(gsb_ctx* ctx, int32_t variant, int32_t schedule, double contr
  *   xb, yb, pb : host, replicas * n_dyn binary32 each, replica-major; overwritten.
  * Synchronises.  Errors: ESTATE, EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE. */
 gsb_status gsb_vjp(gsb_ctx* ctx, int32_t count, float* xb, float* yb, float* pb);
+
+/* gsb_vjp with the cotangents in device memory (replicas * n_dyn binary32 each, replica-
+ * major, caller-owned, overwritten), copied on the context's stream.  Synchronises.
+ * Errors: as gsb_vjp. */
+gsb_status gsb_vjp_device(gsb_ctx* ctx, int32_t count, float* xb, float* yb, float* pb);
 
 /* Device time of the last gsb_step/gsb_run time stepping (the persistent step kernel
  * launches), in milliseconds, measured with HIP events on the context's stream.

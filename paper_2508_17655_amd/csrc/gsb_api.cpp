@@ -38,6 +38,10 @@ gsb_status hip_fail(hipError_t e, const char* what) {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// The status block of a run is 64 words: word 0 is the step kernels' barrier status, word
+// kStateFlagWord the result of the device-side check of a state given by the caller.
+constexpr int kStateFlagWord = 32;
+
 int form_of(int precision) {
   switch (precision) {
     case GSB_PREC_FP8: return kFormFP8;
@@ -183,6 +187,7 @@ struct gsb_ctx {
   int init_mode = GSB_INIT_X;
   int kernel_pref = 0;  // GSB_OPT_STEP_KERNEL
   int grid_pad = 1;     // GSB_OPT_GRID_PAD
+  int lle_from = 0;     // GSB_OPT_LLE_FROM
   hipStream_t stream = nullptr;
   // run
   bool inited = false;
@@ -483,6 +488,12 @@ gsb_status gsb_set(gsb_ctx* c, int32_t option, double v) {
       c->grid_pad = (int)v;
       return GSB_OK;
     }
+    case GSB_OPT_LLE_FROM: {
+      if (!(v >= 0.0 && v <= (double)(1 << 24)) || v != std::floor(v))  // also NaN
+        return fail(GSB_EINVAL, "the LLE window start must be an integer step in [0, 2^24]");
+      c->lle_from = (int)v;
+      return GSB_OK;
+    }
     default:
       return fail(GSB_EINVAL, "unknown or read-only option " + std::to_string(option));
   }
@@ -504,6 +515,7 @@ gsb_status gsb_get(gsb_ctx* c, int32_t option, double* v) {
     case GSB_OPT_INIT_MODE: *v = c->init_mode; return GSB_OK;
     case GSB_OPT_STEP_KERNEL: *v = c->kernel_pref; return GSB_OK;
     case GSB_OPT_GRID_PAD: *v = c->grid_pad; return GSB_OK;
+    case GSB_OPT_LLE_FROM: *v = c->lle_from; return GSB_OK;
     case GSB_OPT_LAMBDA_MAX: ensure_eig(c); *v = c->lmax; return GSB_OK;
     case GSB_OPT_LAMBDA_MIN: ensure_eig(c); *v = c->lmin; return GSB_OK;
     case GSB_OPT_N: *v = c->n_user; return GSB_OK;
@@ -905,16 +917,18 @@ gsb_status gsb_spins(gsb_ctx* c, int8_t* spins) {
   return check_status_word(c);
 }
 
-gsb_status gsb_state(gsb_ctx* c, float* x, float* y, float* p, int32_t* m) {
-  g_err.clear();
+namespace {
+
+// The state of the current run into caller arrays [R][n] (host or device, by `kind`).
+gsb_status state_out(gsb_ctx* c, float* x, float* y, float* p, int32_t* m, hipMemcpyKind kind) {
   if (!c) return fail(GSB_EINVAL, "ctx is NULL");
   if (!c->inited) return fail(GSB_ESTATE, "no run");
   float* src[3] = {c->X, c->Y, c->P};
   float* dst[3] = {x, y, p};
   for (int k = 0; k < 3; ++k)
     if (dst[k])
-      HIP_TRY(hipMemcpy2DAsync(dst[k], (size_t)c->n * 4, src[k], (size_t)c->np * 4, (size_t)c->n * 4, c->R,
-                               hipMemcpyDeviceToHost, c->stream),
+      HIP_TRY(hipMemcpy2DAsync(dst[k], (size_t)c->n * 4, src[k], (size_t)c->np * 4, (size_t)c->n * 4, c->R, kind,
+                               c->stream),
               "copy state");
   gsb_status s = check_status_word(c);
   if (s != GSB_OK) return s;
@@ -922,29 +936,62 @@ gsb_status gsb_state(gsb_ctx* c, float* x, float* y, float* p, int32_t* m) {
   return GSB_OK;
 }
 
-gsb_status gsb_set_state(gsb_ctx* c, const float* x, const float* y, const float* p, int32_t m) {
-  g_err.clear();
+// Replace the state of the current run from caller arrays [R][n]: validated on the host
+// (host arrays) or by a kernel whose flag is read back (device arrays).
+gsb_status state_in(gsb_ctx* c, const float* x, const float* y, const float* p, int32_t m, bool device) {
   if (!c) return fail(GSB_EINVAL, "ctx is NULL");
   if (!c->inited) return fail(GSB_ESTATE, "no run");
   if (!x || !y || !p) return fail(GSB_EINVAL, "x, y and p are required");
   if (m < 0 || m > c->M) return fail(GSB_EINVAL, "m outside [0, M]");
   const size_t cnt = (size_t)c->R * c->n;
-  for (size_t k = 0; k < cnt; ++k) {
-    if (!std::isfinite(x[k]) || !std::isfinite(y[k]) || !std::isfinite(p[k]))
-      return fail(GSB_ENONFINITE, "state has a non-finite entry");
-    if (std::fabs(x[k]) > 1.0f) return fail(GSB_EINVAL, "|x| > 1 in the state (eq. (5) keeps |x| <= 1)");
+  if (device) {
+    unsigned* flag = c->status + kStateFlagWord;
+    unsigned bad = 0;
+    HIP_TRY(launch_check_state(x, y, p, cnt, flag, c->stream), "state check kernel");
+    HIP_TRY(hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, c->stream), "read state check");
+    HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronise");
+    if (bad & 1u) return fail(GSB_ENONFINITE, "state has a non-finite entry");
+    if (bad & 2u) return fail(GSB_EINVAL, "|x| > 1 in the state (eq. (5) keeps |x| <= 1)");
+  } else {
+    for (size_t k = 0; k < cnt; ++k) {
+      if (!std::isfinite(x[k]) || !std::isfinite(y[k]) || !std::isfinite(p[k]))
+        return fail(GSB_ENONFINITE, "state has a non-finite entry");
+      if (std::fabs(x[k]) > 1.0f) return fail(GSB_EINVAL, "|x| > 1 in the state (eq. (5) keeps |x| <= 1)");
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronise");
   }
-  HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronise");
   const float* src[3] = {x, y, p};
   float* dst[3] = {c->X, c->Y, c->P};
   for (int k = 0; k < 3; ++k)
     HIP_TRY(hipMemcpy2DAsync(dst[k], (size_t)c->np * 4, src[k], (size_t)c->n * 4, (size_t)c->n * 4, c->R,
-                             hipMemcpyHostToDevice, c->stream),
+                             device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream),
             "copy state");
   HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronise");
   c->m = m;
   c->energy_valid = false;
   return GSB_OK;
+}
+
+}  // namespace
+
+gsb_status gsb_state(gsb_ctx* c, float* x, float* y, float* p, int32_t* m) {
+  g_err.clear();
+  return state_out(c, x, y, p, m, hipMemcpyDeviceToHost);
+}
+
+gsb_status gsb_state_device(gsb_ctx* c, float* x, float* y, float* p, int32_t* m) {
+  g_err.clear();
+  return state_out(c, x, y, p, m, hipMemcpyDeviceToDevice);
+}
+
+gsb_status gsb_set_state(gsb_ctx* c, const float* x, const float* y, const float* p, int32_t m) {
+  g_err.clear();
+  return state_in(c, x, y, p, m, false);
+}
+
+gsb_status gsb_set_state_device(gsb_ctx* c, const float* x, const float* y, const float* p, int32_t m) {
+  g_err.clear();
+  return state_in(c, x, y, p, m, true);
 }
 
 gsb_status gsb_delta(gsb_ctx* c, double* out) {
@@ -982,6 +1029,8 @@ gsb_status gsb_lle(gsb_ctx* c, int32_t variant, int32_t schedule, double A, cons
   if (replicas < 1 || replicas > (1 << 20)) return fail(GSB_EINVAL, "replicas must be in [1, 2^20]");
   if (steps < 1 || steps > (1 << 24)) return fail(GSB_EINVAL, "steps must be in [1, 2^24]");
   if (renorm_every < 1) return fail(GSB_EINVAL, "renorm_every must be >= 1");
+  const int m_w = c->lle_from;
+  if (m_w >= steps) return fail(GSB_EINVAL, "GSB_OPT_LLE_FROM must be below steps");
   std::vector<float> acol_host;
   try {
     acol_host.assign((size_t)(replicas + kRepPad - 1) / kRepPad * kRepPad, 0.0f);
@@ -1023,11 +1072,17 @@ gsb_status gsb_lle(gsb_ctx* c, int32_t variant, int32_t schedule, double A, cons
     HIP_TRY(hipEventCreate(&c->ev1), "event create");
   }
   HIP_TRY(hipEventRecord(c->ev0, c->stream), "event record");
-  for (int m0 = 0; m0 < steps; m0 += renorm_every) {
-    const int m1 = std::min(steps, m0 + renorm_every);
+  // renormalise every renorm_every steps and at the window start m_w, where the log sums
+  // start again from 0 (the tangent there has unit norm)
+  for (int m0 = 0; m0 < steps;) {
+    int m1 = std::min(steps, m0 + renorm_every);
+    if (m0 < m_w && m1 > m_w) m1 = m_w;
     s = launch_chunks(c, kFormFP32, 2 * rp, false, 0.0f, acol, m0, m1, true);
     if (s != GSB_OK) return s;
     HIP_TRY(launch_tangent_renorm(c->n, c->np, rp, c->X, c->Y, c->P, lg, true, c->stream), "renormalise tangent");
+    if (m1 == m_w)
+      HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(lg), (size_t)rp * 2, 0u, c->stream), "restart log sums");
+    m0 = m1;
   }
   HIP_TRY(hipEventRecord(c->ev1, c->stream), "event record");
   c->timed = true;
@@ -1040,12 +1095,14 @@ gsb_status gsb_lle(gsb_ctx* c, int32_t variant, int32_t schedule, double A, cons
   }
   s = check_status_word(c);
   if (s != GSB_OK) return s;
-  for (int r = 0; r < replicas; ++r) lle[r] = lg_host[r] / ((double)steps * dt);
+  for (int r = 0; r < replicas; ++r) lle[r] = lg_host[r] / ((double)(steps - m_w) * dt);
   return GSB_OK;
 }
 
-gsb_status gsb_vjp(gsb_ctx* c, int32_t count, float* xb, float* yb, float* pb) {
-  g_err.clear();
+namespace {
+
+// The reverse pass; cotangents in and out of caller arrays [R][n] on the host or the device.
+gsb_status vjp_impl(gsb_ctx* c, int32_t count, float* xb, float* yb, float* pb, bool device) {
   if (!c || !xb || !yb || !pb) return fail(GSB_EINVAL, "NULL argument");
   if (!c->inited) return fail(GSB_ESTATE, "no run");
   if (c->variant != GSB_BSB && c->variant != GSB_GBSB)
@@ -1084,7 +1141,7 @@ gsb_status gsb_vjp(gsb_ctx* c, int32_t count, float* xb, float* yb, float* pb) {
   const float* src[3] = {xb, yb, pb};
   for (int k = 0; k < 3; ++k)
     HIP_TRY(hipMemcpy2DAsync(cot + k * arr, (size_t)c->np * 4, src[k], (size_t)nd * 4, (size_t)nd * 4, c->R,
-                             hipMemcpyHostToDevice, c->stream),
+                             device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream),
             "upload cotangents");
   const int max_wg = max_coresident_adjoint();
   const int nb = c->np / tile_rows_kind(kKindGeneric);
@@ -1096,9 +1153,21 @@ gsb_status gsb_vjp(gsb_ctx* c, int32_t count, float* xb, float* yb, float* pb) {
   float* dst[3] = {xb, yb, pb};
   for (int k = 0; k < 3; ++k)
     HIP_TRY(hipMemcpy2DAsync(dst[k], (size_t)nd * 4, cot + k * arr, (size_t)c->np * 4, (size_t)nd * 4, c->R,
-                             hipMemcpyDeviceToHost, c->stream),
+                             device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream),
             "download cotangents");
   return check_status_word(c);
+}
+
+}  // namespace
+
+gsb_status gsb_vjp(gsb_ctx* c, int32_t count, float* xb, float* yb, float* pb) {
+  g_err.clear();
+  return vjp_impl(c, count, xb, yb, pb, false);
+}
+
+gsb_status gsb_vjp_device(gsb_ctx* c, int32_t count, float* xb, float* yb, float* pb) {
+  g_err.clear();
+  return vjp_impl(c, count, xb, yb, pb, true);
 }
 
 gsb_status gsb_last_step_ms(gsb_ctx* c, double* ms) {

@@ -39,6 +39,10 @@ struct BatchArgs {
 
 // ---- launchers (all asynchronous on `stream`) ----
 hipError_t launch_fill_u32(unsigned* p, size_t count, unsigned v, hipStream_t stream);
+// *flag = 0, then bit 0 set for a non-finite entry of x, y or p and bit 1 for |x| > 1
+// among `count` elements of each (device arrays).
+hipError_t launch_check_state(const float* x, const float* y, const float* p, size_t count, unsigned* flag,
+                              hipStream_t stream);
 hipError_t launch_encode_j(int form, bool fp4, const float* j32, int np, void* jf, hipStream_t stream);
 // r_m = fl32(1 / (M - m)) for m < steps (linear schedule), else 0, computed on the device.
 hipError_t launch_rtab(float* rtab, int steps, bool linear, hipStream_t stream);

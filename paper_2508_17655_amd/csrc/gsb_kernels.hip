@@ -822,6 +822,22 @@ __global__ void k_fill_u32(unsigned* p, size_t count, unsigned v) {
     p[t] = v;
 }
 
+// Validity of a caller's state on the device (the checks gsb_set_state makes on the host):
+// bit 0 of *flag for a non-finite entry of x, y or p, bit 1 for |x| > 1 (eq. (5) keeps
+// |x| <= 1).  One atomic per wave that found something.
+__global__ void k_check_state(const float* x, const float* y, const float* p, size_t count, unsigned* flag) {
+  unsigned bad = 0;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (size_t)gridDim.x * blockDim.x) {
+    const float xv = x[t], yv = y[t], pv = p[t];
+    if (!__builtin_isfinite(xv) || !__builtin_isfinite(yv) || !__builtin_isfinite(pv)) bad |= 1u;
+    else if (__builtin_fabsf(xv) > 1.0f) bad |= 2u;
+  }
+  const unsigned long long any1 = __builtin_amdgcn_ballot_w64((bad & 1u) != 0);
+  const unsigned long long any2 = __builtin_amdgcn_ballot_w64((bad & 2u) != 0);
+  if ((any1 | any2) != 0 && (threadIdx.x & 63) == 0)
+    __hip_atomic_fetch_or(flag, (any1 ? 1u : 0u) | (any2 ? 2u : 0u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Schedule table r_m = 1 / (M - m) of eqs. (6), (7), the binary64 quotient rounded to
 // binary32 once (the same bits as the host table: both divisions are correctly rounded);
 // all zero for the constant schedule.
@@ -1331,6 +1347,15 @@ const void* steps_kernel_for(int form, int kind, int np, bool discrete) {
 // ---------------------------------------------------------------------------------------
 hipError_t launch_fill_u32(unsigned* p, size_t count, unsigned v, hipStream_t stream) {
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(count, 256)), dim3(256), 0, stream, p, count, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_state(const float* x, const float* y, const float* p, size_t count, unsigned* flag,
+                              hipStream_t stream) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, stream, flag, (size_t)1, 0u);
+  if (count == 0) return hipGetLastError();
+  const int grid = std::min(grid_for(count, 256), 1024);
+  hipLaunchKernelGGL(k_check_state, dim3(grid), dim3(256), 0, stream, x, y, p, count, flag);
   return hipGetLastError();
 }
 

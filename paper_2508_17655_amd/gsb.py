@@ -25,7 +25,7 @@ GSB_PREC_FP32, GSB_PREC_BF16X2, GSB_PREC_FP8, GSB_PREC_FIX16 = 0, 1, 2, 3
 GSB_INIT_X, GSB_INIT_XY, GSB_INIT_PM01, GSB_INIT_PAIRS = 0, 1, 2, 3
 (GSB_OPT_C, GSB_OPT_PRECISION, GSB_OPT_INIT_MODE, GSB_OPT_LAMBDA_MAX, GSB_OPT_LAMBDA_MIN, GSB_OPT_N,
  GSB_OPT_STEP, GSB_OPT_REPLICAS, GSB_OPT_DT_STABLE, GSB_OPT_N_DYN, GSB_OPT_STEP_KERNEL,
- GSB_OPT_GRID_PAD) = range(12)
+ GSB_OPT_GRID_PAD, GSB_OPT_LLE_FROM) = range(13)
 
 (GSB_BATCH_C, GSB_BATCH_DT, GSB_BATCH_LAMBDA_MAX, GSB_BATCH_LAMBDA_MIN, GSB_BATCH_TILE_ROWS, GSB_BATCH_STEP_US,
  GSB_BATCH_N, GSB_BATCH_GRAPH, GSB_BATCH_INIT_MODE, GSB_BATCH_COUNT, GSB_BATCH_REPLICAS, GSB_BATCH_GRID,
@@ -40,7 +40,8 @@ STATUS_NAMES = {0: "GSB_OK", -1: "GSB_EINVAL", -2: "GSB_ENOTSYM", -3: "GSB_EDIAG
 # Every symbol include/gsb.h declares.
 SYMBOLS = ("gsb_create", "gsb_destroy", "gsb_set", "gsb_get", "gsb_set_stream", "gsb_workspace_size",
            "gsb_bind_workspace", "gsb_init", "gsb_step", "gsb_run", "gsb_run_noalloc", "gsb_energy", "gsb_best", "gsb_spins",
-           "gsb_state", "gsb_set_state", "gsb_delta", "gsb_lle_workspace_size", "gsb_lle", "gsb_vjp", "gsb_last_step_ms",
+           "gsb_state", "gsb_set_state", "gsb_state_device", "gsb_set_state_device", "gsb_delta",
+           "gsb_lle_workspace_size", "gsb_lle", "gsb_vjp", "gsb_vjp_device", "gsb_last_step_ms",
            "gsb_batch_create", "gsb_batch_destroy", "gsb_batch_set_stream", "gsb_batch_workspace_size",
            "gsb_batch_bind_workspace", "gsb_batch_set_coupling", "gsb_batch_set", "gsb_batch_get", "gsb_batch_autotune",
            "gsb_batch_run", "gsb_batch_energy", "gsb_batch_best", "gsb_batch_state", "gsb_batch_last_ms",
@@ -89,10 +90,13 @@ def load_library(path: str = LIB_PATH):
         "gsb_spins": (i32, [vp, vp]),
         "gsb_state": (i32, [vp, vp, vp, vp, ctypes.POINTER(i32)]),
         "gsb_set_state": (i32, [vp, vp, vp, vp, i32]),
+        "gsb_state_device": (i32, [vp, vp, vp, vp, ctypes.POINTER(i32)]),
+        "gsb_set_state_device": (i32, [vp, vp, vp, vp, i32]),
         "gsb_delta": (i32, [vp, vp]),
         "gsb_lle_workspace_size": (i32, [vp, i32, i32, ctypes.POINTER(sz)]),
         "gsb_lle": (i32, [vp, i32, i32, dbl, vp, dbl, i32, i32, u64, u64, i32, vp, vp]),
         "gsb_vjp": (i32, [vp, i32, vp, vp, vp]),
+        "gsb_vjp_device": (i32, [vp, i32, vp, vp, vp]),
         "gsb_last_step_ms": (i32, [vp, ctypes.POINTER(dbl)]),
         "gsb_batch_create": (i32, [i32, vp, i32, ctypes.POINTER(vp)]),
         "gsb_batch_destroy": (None, [vp]),
@@ -241,6 +245,36 @@ def gsb_set_state(ctx, x: np.ndarray, y: np.ndarray, p: np.ndarray, m: int) -> N
     y = np.ascontiguousarray(y, dtype=np.float32)
     p = np.ascontiguousarray(p, dtype=np.float32)
     _check(load_library().gsb_set_state(ctx, _ptr(x), _ptr(y), _ptr(p), m), "gsb_set_state")
+
+
+def _device_arrays(ctx, *ts):
+    """Device pointers of float32 tensors [replicas, n_dyn], contiguous, on a GPU."""
+    R = int(gsb_get(ctx, GSB_OPT_REPLICAS))
+    n = int(gsb_get(ctx, GSB_OPT_N_DYN))
+    out = []
+    for t in ts:
+        if not t.is_cuda or t.dtype.itemsize != 4 or not t.dtype.is_floating_point:
+            raise ValueError("device state arrays must be float32 tensors on the GPU")
+        if tuple(t.shape) != (R, n) or not t.is_contiguous():
+            raise ValueError(f"device state arrays must be contiguous [{R}, {n}]")
+        out.append(ctypes.c_void_p(t.data_ptr()))
+    return out
+
+
+def gsb_state_device(ctx, x, y, p) -> int:
+    """The current state into float32 tensors x, y, p [replicas, n_dyn] on the device; returns m."""
+    m = ctypes.c_int32()
+    _check(load_library().gsb_state_device(ctx, *_device_arrays(ctx, x, y, p), ctypes.byref(m)), "gsb_state_device")
+    return m.value
+
+
+def gsb_set_state_device(ctx, x, y, p, m: int) -> None:
+    _check(load_library().gsb_set_state_device(ctx, *_device_arrays(ctx, x, y, p), m), "gsb_set_state_device")
+
+
+def gsb_vjp_device(ctx, count: int, xb, yb, pb) -> None:
+    """gsb_vjp on float32 tensors [replicas, n_dyn] on the device, overwritten in place."""
+    _check(load_library().gsb_vjp_device(ctx, count, *_device_arrays(ctx, xb, yb, pb)), "gsb_vjp_device")
 
 
 def gsb_delta(ctx) -> np.ndarray:
@@ -595,10 +629,13 @@ class GSB:
         return gsb_delta(self.ctx)
 
     def lle(self, variant, *, A=0.0, dt: float, replicas: int, steps: int, seed: int, tangent_seed: int,
-            renorm_every: int = 10, schedule: int = GSB_SCHED_LINEAR, want_state: bool = False):
-        """Largest-Lyapunov-exponent estimates; A is one value or one per replica."""
+            renorm_every: int = 10, schedule: int = GSB_SCHED_LINEAR, want_state: bool = False,
+            window_from: int = 0):
+        """Largest-Lyapunov-exponent estimates; A is one value or one per replica.  The
+        growth is counted from step `window_from` on (GSB_OPT_LLE_FROM)."""
         v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
         per = None if np.isscalar(A) else np.asarray(A, dtype=np.float64)
+        gsb_set(self.ctx, GSB_OPT_LLE_FROM, window_from)
         self._prepare(replicas, steps, lle=True)
         return gsb_lle(self.ctx, v, schedule, float(A) if per is None else 0.0, per, dt, replicas, steps, seed,
                        tangent_seed, renorm_every, want_state)
@@ -607,8 +644,24 @@ class GSB:
         gsb_set_stream(self.ctx, self._torch.cuda.current_stream().cuda_stream)
         return gsb_vjp(self.ctx, count, xb, yb, pb)
 
+    # the device-memory forms (torch tensors on the GPU, on torch's current stream)
+    def state_device(self, x, y, p) -> int:
+        gsb_set_stream(self.ctx, self._torch.cuda.current_stream().cuda_stream)
+        return gsb_state_device(self.ctx, x, y, p)
+
+    def set_state_device(self, x, y, p, m: int) -> None:
+        gsb_set_stream(self.ctx, self._torch.cuda.current_stream().cuda_stream)
+        gsb_set_state_device(self.ctx, x, y, p, m)
+
+    def vjp_device(self, count: int, xb, yb, pb) -> None:
+        gsb_set_stream(self.ctx, self._torch.cuda.current_stream().cuda_stream)
+        gsb_vjp_device(self.ctx, count, xb, yb, pb)
+
     def last_step_ms(self) -> float:
         return gsb_last_step_ms(self.ctx)
 
     def get(self, option: int) -> float:
         return gsb_get(self.ctx, option)
+
+    def set(self, option: int, value: float) -> None:
+        gsb_set(self.ctx, option, value)

@@ -81,34 +81,36 @@ def test_vjp_matches_oracle_with_walls():
     g.close()
 
 
-def test_checkpointed_segments_equal_one_pass_and_finite_differences():
+def _checkpointed_grads(device):
+    """Gradients of a weighted sum of x(T), y(T) through autograd segments of 5 steps, the
+    one-pass reverse reference (host gsb_vjp over all M steps), and a central difference."""
     import torch
 
     from paper_2508_17655_amd import autograd as sbad
 
-    gsb = _gsb()
     n, R, M, dt = 200, 8, 15, 0.5
     J = instances.dense_pm1(n, 11).astype(np.float64)
     c = 0.5 / np.linalg.eigvalsh(J)[-1]
-    g, x0, y0, p0 = sbad.start(J, "gbsb", A=0.3, dt=dt, replicas=R, steps=M, seed=12, c=c)
+    g, x0, y0, p0 = sbad.start(J, "gbsb", A=0.3, dt=dt, replicas=R, steps=M, seed=12, c=c, device=device)
+    assert x0.device.type == torch.device(device).type
     rng = np.random.default_rng(13)
-    wgt = torch.from_numpy(rng.standard_normal((R, n)).astype(np.float32))
+    wgt = torch.from_numpy(rng.standard_normal((R, n)).astype(np.float32)).to(device)
 
     def loss(x, y, p, every):
         xT, yT, pT = sbad.trajectory(g, x, y, p, M, every=every)
+        assert xT.device == x0.device
         return (wgt * xT).sum() + 0.5 * (wgt * yT).sum()
 
     xs = x0.clone().requires_grad_(True)
     ys = y0.clone().requires_grad_(True)
     L = loss(xs, ys, p0, every=5)
     L.backward()
+    assert xs.grad.device == x0.device
     # one reverse pass over all M steps
-    g.set_state(x0.numpy(), y0.numpy(), p0.numpy(), 0)
-    gx, gy, _ = g.vjp(M, wgt.numpy(), 0.5 * wgt.numpy(), np.zeros((R, n), np.float32))
-    np.testing.assert_allclose(xs.grad.numpy(), gx, rtol=1e-5, atol=1e-6 * np.max(np.abs(gx)))
-    np.testing.assert_allclose(ys.grad.numpy(), gy, rtol=1e-5, atol=1e-6 * np.max(np.abs(gy)))
-    # central differences along a random direction (binary32, no wall in the window)
-    u = torch.from_numpy(rng.standard_normal((R, n)).astype(np.float32))
+    g.set_state(x0.cpu().numpy(), y0.cpu().numpy(), p0.cpu().numpy(), 0)
+    wn = wgt.cpu().numpy()
+    gx, gy, _ = g.vjp(M, wn, 0.5 * wn, np.zeros((R, n), np.float32))
+    u = torch.from_numpy(rng.standard_normal((R, n)).astype(np.float32)).to(device)
     u /= u.norm()
     eps = 1e-3
     with torch.no_grad():
@@ -116,7 +118,61 @@ def test_checkpointed_segments_equal_one_pass_and_finite_differences():
         lm = float(loss(x0 - eps * u, y0, p0, every=M))
     fd = (lp - lm) / (2 * eps)
     an = float((xs.grad * u).sum())
-    assert abs(fd - an) < 1e-2 * abs(an) + 1e-3
+    g.close()
+    return xs.grad.cpu().numpy(), ys.grad.cpu().numpy(), gx, gy, fd, an
+
+
+def test_checkpointed_segments_equal_one_pass_and_finite_differences():
+    """Host tensors and CUDA tensors (the device-resident path: no host copies of the state
+    or the cotangents) give the same gradients, bit for bit, equal to the one-pass reverse
+    pass and to central differences."""
+    res = {}
+    for device in ("cpu", "cuda"):
+        gxs, gys, gx, gy, fd, an = _checkpointed_grads(device)
+        np.testing.assert_allclose(gxs, gx, rtol=1e-5, atol=1e-6 * np.max(np.abs(gx)))
+        np.testing.assert_allclose(gys, gy, rtol=1e-5, atol=1e-6 * np.max(np.abs(gy)))
+        assert abs(fd - an) < 1e-2 * abs(an) + 1e-3
+        res[device] = (gxs, gys)
+    np.testing.assert_array_equal(res["cpu"][0], res["cuda"][0])
+    np.testing.assert_array_equal(res["cpu"][1], res["cuda"][1])
+
+
+def test_device_state_round_trip_and_checks():
+    import torch
+
+    gsb = _gsb()
+    n, R = 150, 6
+    J = instances.dense_pm1(n, 3)
+    g = gsb.GSB(J, precision="fp32")
+    g.init("gbsb", A=0.2, dt=0.5, replicas=R, steps=20, seed=4)
+    g.step(7)
+    xh, yh, ph, m = g.state()
+    x, y, p = (torch.empty((R, n), dtype=torch.float32, device="cuda") for _ in range(3))
+    assert g.state_device(x, y, p) == 7
+    for a, b in ((x, xh), (y, yh), (p, ph)):
+        np.testing.assert_array_equal(a.cpu().numpy(), b)
+    # a state set from the device continues as the host one does
+    g.set_state_device(x, y, p, 7)
+    g.step(5)
+    x1 = g.state()[0]
+    g.set_state(xh, yh, ph, 7)
+    g.step(5)
+    np.testing.assert_array_equal(g.state()[0], x1)
+    # the device-side checks: non-finite entries, |x| > 1, shapes; the state is left alone
+    before = g.state()
+    bad = y.clone()
+    bad[2, 5] = float("nan")
+    with pytest.raises(gsb.GsbError, match="ENONFINITE"):
+        g.set_state_device(x, bad, p, 3)
+    big = x.clone()
+    big[R - 1, n - 1] = 1.5
+    with pytest.raises(gsb.GsbError, match="EINVAL"):
+        g.set_state_device(big, y, p, 3)
+    with pytest.raises(ValueError):
+        g.set_state_device(x[:, :-1].contiguous(), y, p, 3)
+    after = g.state()
+    for a, b in zip(before, after):
+        np.testing.assert_array_equal(np.asarray(a), np.asarray(b))
     g.close()
 
 

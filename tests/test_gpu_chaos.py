@@ -86,6 +86,43 @@ def test_tangent_matches_oracle_short_horizon(variant, schedule):
     g.close()
 
 
+def test_lle_window_matches_oracle():
+    """GSB_OPT_LLE_FROM: growth counted from step m_w, against the oracle's tangent run over
+    [0, m_w) followed by one over [m_w, T) from the state reached (binary32 vs binary64,
+    no wall contacts in the window)."""
+    gsb = _gsb()
+    n, R, T, m_w, dt, seed, tseed = 250, 40, 25, 11, 0.5, 7, 99
+    J = instances.dense_pm1(n, 8)
+    lam = np.linalg.eigvalsh(J.astype(np.float64))
+    c = 0.5 / lam[-1]
+    A = np.linspace(0.0, 0.6, R)
+    g = gsb.GSB(J, c=c)
+    lle, st = g.lle("gbsb", A=A, dt=dt, replicas=R, steps=T, seed=seed, tangent_seed=tseed, renorm_every=7,
+                    want_state=True, window_from=m_w)
+    assert g.get(gsb.GSB_OPT_LLE_FROM) == m_w
+    x0, y0 = oracle.init_state(n, R, seed, oracle.INIT_X)
+    dx0 = _tangent_start(n, R, tseed)
+    ref_lg = np.empty(R)
+    for r in range(R):
+        kw = dict(A=float(A[r]), dt=dt, c=c, steps=T, renorm=7)
+        x1, y1, p1, dx1, dy1, dp1, _ = oracle.tangent_run(J.astype(np.float64), oracle.GBSB, x=x0[r:r + 1],
+                                                          y=y0[r:r + 1], dx=dx0[r:r + 1], m_end=m_w, **kw)
+        out = oracle.tangent_run(J.astype(np.float64), oracle.GBSB, x=x1, y=y1, p=p1, dx=dx1, dy=dy1, dp=dp1,
+                                 m_begin=m_w, **kw)
+        assert np.max(np.abs(out[0])) < 0.95, "the window must stay away from the walls"
+        ref_lg[r] = out[6][0]
+    np.testing.assert_allclose(lle * (T - m_w) * dt, ref_lg, atol=2e-5, rtol=0)
+    # the whole-run estimate is back once the option is 0; a window start at or past the end
+    # is rejected
+    whole = g.lle("gbsb", A=A, dt=dt, replicas=R, steps=T, seed=seed, tangent_seed=tseed, renorm_every=7)
+    assert not np.allclose(whole, lle)
+    with pytest.raises(gsb.GsbError):
+        g.lle("gbsb", A=A, dt=dt, replicas=R, steps=T, seed=seed, tangent_seed=tseed, window_from=T)
+    with pytest.raises(gsb.GsbError):
+        g.set(gsb.GSB_OPT_LLE_FROM, -1)
+    g.close()
+
+
 def test_lle_sweep_full_size_invariants():
     """N = 2000 dense +-1 (the benchmark instance), 8 control strengths x 8 replicas."""
     gsb = _gsb()

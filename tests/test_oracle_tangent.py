@@ -10,6 +10,9 @@
   log growth equals the one obtained from the eigenmodes of J (numpy eigh) and 2 x 2
   mode matrices, and tends to ln r_max / dt with r^2 - (2 - k dt^2) r + 1 = 0,
   k = p - c lambda_max.
+- The window estimate (growth counted from a step m_w on) against the same eigenmode
+  propagation with its log sums started at m_w, and the growths of two intervals adding
+  up to that of their union.
 """
 import numpy as np
 import pytest
@@ -161,6 +164,43 @@ def test_lle_linear_regime_closed_form():
     r_max = (q + np.sqrt(q * q - 4.0)) / 2.0
     lle = lg[0] / (T * dt)
     assert abs(lle - np.log(r_max) / dt) < 0.02 * np.log(r_max) / dt
+
+
+def test_lle_window_is_the_growth_after_its_start():
+    """The post-bifurcation window estimate: the tangent run over [0, m_w), then over
+    [m_w, T) from the state reached, counts only the second interval's growth.  In the
+    linear regime of the test above that is the eigenmode propagation with the log sums
+    started at m_w; and the two intervals' growths add up to the one-interval growth."""
+    n, T, m_w, dt = 32, 300, 120, 0.5
+    J = _sym_pm1(n, 23)
+    lam, V = np.linalg.eigh(J)
+    c = 1.5 / lam[-1]
+    rng = np.random.default_rng(24)
+    u = rng.standard_normal(n)
+    z = np.zeros((1, n))
+    one = np.ones((1, n))
+    kw = dict(dt=dt, c=c, steps=T, schedule=oracle.SCHED_CONSTANT, renorm=10)
+    *_, lg_all = oracle.tangent_run(J, oracle.BSB, x=z, y=z, p=one, dx=u[None, :], **kw)
+    x1, y1, p1, dx1, dy1, dp1, lg_a = oracle.tangent_run(J, oracle.BSB, x=z, y=z, p=one, dx=u[None, :], m_end=m_w,
+                                                         **kw)
+    *_, lg_b = oracle.tangent_run(J, oracle.BSB, x=x1, y=y1, p=p1, dx=dx1, dy=dy1, dp=dp1, m_begin=m_w, **kw)
+    assert abs((lg_a[0] + lg_b[0]) - lg_all[0]) < 1e-11 * abs(lg_all[0])
+    a = V.T @ (u / np.linalg.norm(u))
+    b = np.zeros(n)
+    logs = 0.0
+    k = 1.0 - c * lam
+    for t in range(T):
+        a, b = (1.0 - k * dt * dt) * a + dt * b, -k * dt * a + b
+        if t + 1 == m_w:  # the window starts: unit norm, log sums from 0
+            s = np.sqrt(np.sum(a * a) + np.sum(b * b))
+            a /= s
+            b /= s
+        elif t + 1 > m_w and ((t + 1 - m_w) % 10 == 0 or t + 1 == T):
+            s = np.sqrt(np.sum(a * a) + np.sum(b * b))
+            logs += np.log(s)
+            a /= s
+            b /= s
+    assert abs(lg_b[0] - logs) < 1e-9 * abs(logs)
 
 
 def test_gbsb_at_zero_control_is_bsb():
