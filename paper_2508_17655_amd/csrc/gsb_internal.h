@@ -58,7 +58,7 @@ int max_coresident_workgroups(int form, int kind, int np, bool tangent = false);
 // The register-resident FP8 kernel for nks = np / 128 in {4, 8, 12, 16}, else nullptr.
 const void* steps_kernel_rj(int nks, bool discrete);
 const void* steps_kernel_ws(int nks, bool discrete);
-size_t steps_ws_lds_bytes(int np);
+size_t steps_ws_lds_bytes(int np, bool discrete);
 // Reverse pass of the binary32 dynamics over a recorded tape (see k_adjoint); a.x, a.y,
 // a.p carry the cotangents in and out.  Occupancy limit of that kernel.
 hipError_t launch_adjoint(const StepArgs& a, hipStream_t stream);

@@ -1310,8 +1310,8 @@ const void* steps_kernel() {
 // The generic tile keeps its 64 rows of J in LDS when they fit beside the kernel's few
 // static bytes: int8 J (FIX16, 64 np bytes) or FP4 J (FP8, 32 np bytes).
 constexpr size_t kJLdsMax = 159 * 1024;
-size_t steps_lds_bytes(int form, int kind, int np) {
-  if (kind == kKindWaveSpec) return steps_ws_lds_bytes(np);
+size_t steps_lds_bytes(int form, int kind, int np, bool discrete) {
+  if (kind == kKindWaveSpec) return steps_ws_lds_bytes(np, discrete);
   if (kind != kKindGeneric) return 0;
   const size_t bytes = form == kFormFIX16 ? (size_t)64 * np : (form == kFormFP8 ? (size_t)32 * np : 0);
   return bytes <= kJLdsMax ? bytes : 0;
@@ -1323,11 +1323,11 @@ const void* steps_kernel_disc(int form, int kind, int np) {
   if (kind == kKindWaveSpec) return steps_kernel_ws(np / kKS, DISC);
   switch (form) {
     case kFormFP8:
-      return steps_lds_bytes(form, kind, np) ? reinterpret_cast<const void*>(&k_steps<kFormFP8, DISC, false, true>)
+      return steps_lds_bytes(form, kind, np, DISC) ? reinterpret_cast<const void*>(&k_steps<kFormFP8, DISC, false, true>)
                                              : steps_kernel<kFormFP8, DISC>();
     case kFormBF16X2: return steps_kernel<kFormBF16X2, DISC>();
     case kFormFIX16:
-      return steps_lds_bytes(form, kind, np) ? reinterpret_cast<const void*>(&k_steps<kFormFIX16, DISC, false, true>)
+      return steps_lds_bytes(form, kind, np, DISC) ? reinterpret_cast<const void*>(&k_steps<kFormFIX16, DISC, false, true>)
                                              : steps_kernel<kFormFIX16, DISC>();
     default: return steps_kernel<kFormFP32, DISC>();
   }
@@ -1417,7 +1417,7 @@ int max_coresident_workgroups(int form, int kind, int np, bool tangent) {
   for (int disc = 0; disc < 2; ++disc) {
     const void* k = steps_kernel_for(form, kind, np, disc != 0);
     if (!k) return 0;
-    const size_t lds = steps_lds_bytes(form, kind, np);
+    const size_t lds = steps_lds_bytes(form, kind, np, disc != 0);
     if (lds > 0 && hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
       return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads_kind(kind), lds) != hipSuccess) return 0;
@@ -1448,7 +1448,7 @@ hipError_t launch_steps(int form, int kind, const StepArgs& a, hipStream_t strea
   if (tangent && (form != kFormFP32 || kind != kKindGeneric || a.discrete)) return hipErrorInvalidValue;
   const void* k = tangent ? steps_kernel_tangent() : steps_kernel_for(form, kind, a.np, a.discrete != 0);
   if (!k) return hipErrorInvalidValue;
-  const size_t lds = steps_lds_bytes(form, kind, a.np);
+  const size_t lds = steps_lds_bytes(form, kind, a.np, a.discrete != 0);
   if (lds > 0) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;

@@ -18,7 +18,9 @@
 // eq. (5) keeps x there).  Operand k (k = 0 at the launch's first step) sits in buffer
 // k % 2 with tag (k / 2) % 2, so a buffer holds either the operand a product wave wants or
 // the one two steps older, whose tag differs.  Each product wave strips and checks the tag
-// of every word it loads and loads again while any is stale: a word is written by one
+// of every word it loads and loads again while any is stale (the sign operand of dSB and
+// GdSB carries the tag in every byte and is not stripped: tagged, its bytes are +-256
+// instead of +-1, which the MFMA's E8M0 block scale of 2^-8 undoes exactly): a word is written by one
 // 32-bit store and so is seen whole or not at all, and no group counter is needed between
 // steps.  The launch's first operand is behind the group counter (buffer 1 is cleared to
 // the stale tag under the same counter).  Where the group spans XCDs, whose L2 caches are
@@ -35,7 +37,13 @@ constexpr int kWsThreads = 512;
 // k-steps of J per product wave in VGPRs; the rest sit in LDS.  The register budget of a
 // wave at two waves per SIMD is 256 VGPRs and AGPRs together, shared by both roles (the
 // compiler splits it evenly as soon as a kernel uses AGPRs), so all of it stays in VGPRs.
-constexpr int kWsRegKSteps = 8;
+// The sign product hands its product over in f16 (integers of magnitude <= 2048, exact),
+// which leaves the LDS room for one more k-step of J; the registers that frees hold one
+// more operand fragment in flight (a second one made the J registers spill).
+constexpr int ws_reg_ksteps(bool disc) { return disc ? 7 : 8; }
+constexpr int ws_prefetch(bool disc) { return disc ? 6 : 5; }
+// bytes of one product wave's slot: 4 row tiles x 64 lanes x 4 values (f16 or f32)
+constexpr int ws_slot_bytes(bool disc) { return 4 * 64 * (disc ? 8 : 16); }
 constexpr unsigned kLdsSpinLimit = 1u << 27;  // LDS polls before giving up (seconds)
 constexpr int kPwAbandoned = -1000000;        // s_pw_go when the poller gave up
 
@@ -61,9 +69,9 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
   __shared__ int s_pw_arrived;  // product waves that have handed over their product
   __shared__ int s_pw_go;       // product waves may load the operand of this sequence number
   // operand fragments in flight per product wave (the K loop is fully unrolled, so the
-  // depth need not divide the k-steps); five is what the registers hold without spills
-  constexpr int kPF = NKS < 5 ? NKS : 5;
-  constexpr int NR = NKS < kWsRegKSteps ? NKS : kWsRegKSteps;  // J k-steps in registers
+  // depth need not divide the k-steps): what the registers hold without spills
+  constexpr int kPF = NKS < ws_prefetch(DISC) ? NKS : ws_prefetch(DISC);
+  constexpr int NR = NKS < ws_reg_ksteps(DISC) ? NKS : ws_reg_ksteps(DISC);  // J k-steps in registers
   constexpr int NL = NKS - NR;                                 // J k-steps in LDS
 
   const int tid = threadIdx.x, lane = tid & 63;
@@ -83,10 +91,9 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
   // per generation every update wave of the group arrives once
   const unsigned gen = 4u * (unsigned)a.nb;
 
-  // LDS: J tails [w][row tile][NL][1 KiB], then the product slots [w][row tile][lane][4 f32]
+  // LDS: J tails [w][row tile][NL][1 KiB], then the product slots [w][row tile][lane][4 values]
   uint8_t* jtail = lds;
-  float* slots = reinterpret_cast<float*>(lds + (size_t)16 * NL * 1024);
-  float* slot = slots + (size_t)w * 4 * 64 * 4;
+  uint8_t* slot = lds + (size_t)16 * NL * 1024 + (size_t)w * ws_slot_bytes(DISC);
 
   v4i jr[4][NR];
   if (product_wave) {
@@ -174,13 +181,23 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
       return true;
     };
     // strip the step tag from fragments and report (for the whole wave) whether any of
-    // their words was stale: pat is the expected tag, cmask 0x40 (or 0: no check)
+    // their words was stale: pat is the expected tag, cmask 0x40 (or 0: no check).  The
+    // sign product keeps its tags: there the tag is in every byte of a word, a tagged +-1
+    // byte is +-256 exactly, and the MFMA's block scale of the operand (2^-8 for a tagged
+    // operand) takes the factor back exactly, so the words are only checked.
     auto strip = [&](v8i& b, unsigned pat) -> unsigned {
       unsigned o = 0;
+      if constexpr (DISC) {
+        // (b0 ^ pat) | (b1 ^ pat) per pair of words: one bitop3 each (truth table 0x7E)
 #pragma unroll
-      for (int d = 0; d < 8; ++d) {
-        b[d] ^= (int)pat;
-        o |= (unsigned)b[d];
+        for (int d = 0; d < 8; d += 2)
+          o |= __builtin_amdgcn_bitop3_b32((unsigned)b[d], (unsigned)b[d + 1], pat, 0x7E);
+      } else {
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+          b[d] ^= (int)pat;
+          o |= (unsigned)b[d];
+        }
       }
       return o;
     };
@@ -258,6 +275,8 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
       // the launch's first operand is behind the group counter and carries no tag
       const unsigned cmask = s > 0 ? 0x40u : 0u;
       const unsigned pat = ((s >> 1) & 1) ? cmask : 0u;
+      // E8M0 block scale of the operand: 2^0, or 2^-8 for a tagged sign operand
+      const int scale_q = DISC && pat ? 127 - 8 : 127;
 #pragma unroll
       for (int sub = 0; sub < 2; ++sub) {
         const int seq = 2 * s + sub + 1;
@@ -287,7 +306,7 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
           for (int rt = 0; rt < 4; ++rt) {
             const v4i f = ks < NR ? jr[rt][ks < NR ? ks : 0] : jl[(ks - NR) & 1][rt];
             acc[rt] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(cat(f, f), bq[ks % kPF], acc[rt], 4, 0, 0,
-                                                                       127, 0, 127);
+                                                                       127, 0, scale_q);
           }
           asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]));
           if (ks + kPF < NKS) load_b(sub, cur, ks + kPF, bq[ks % kPF]);
@@ -308,7 +327,17 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
           }
           if (!alive) break;
 #pragma unroll
-          for (int rt = 0; rt < 4; ++rt) *reinterpret_cast<v4f*>(slot + (rt * 64 + lane) * 4) = acc[rt];
+          for (int rt = 0; rt < 4; ++rt) {
+            if constexpr (DISC) {
+              // integers of magnitude <= 2048: f16 holds them exactly (round toward zero
+              // leaves them unchanged)
+              const v2u h{__builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(acc[rt][0], acc[rt][1])),
+                          __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(acc[rt][2], acc[rt][3]))};
+              *reinterpret_cast<v2u*>(slot + (size_t)(rt * 64 + lane) * 8) = h;
+            } else {
+              *reinterpret_cast<v4f*>(slot + (size_t)(rt * 64 + lane) * 16) = acc[rt];
+            }
+          }
           __hip_atomic_store(&s_ready[w], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         // across XCDs, the operand of the next K loop is loaded behind the group counter
@@ -395,6 +424,8 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
                                     xs[sub][rt], tag);
   };
 
+  // the step tag: bit 6 of the word's first byte, or of every byte for the sign operand
+  constexpr unsigned kTag = DISC ? 0x40404040u : 0x40u;
   bool alive = alive0;
   if (alive) {
 #pragma unroll
@@ -405,7 +436,7 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
         store_operand<kFormFP8, DISC>(a.q, a.q_buf_bytes, NKS, row0 + rt * 16, col0 + sub * 16, lane,
                                       xs[sub][rt]);
         store_operand<kFormFP8, DISC>(a.q + a.q_buf_bytes, a.q_buf_bytes, NKS, row0 + rt * 16, col0 + sub * 16,
-                                      lane, xs[sub][rt], 0x40u);
+                                      lane, xs[sub][rt], kTag);
       }
     arrive(ctr0);
     arrive(ctr1);
@@ -413,7 +444,7 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
   for (int s = 0; alive && s < steps; ++s) {
     const int m = a.m_begin + s;
     uint8_t* qnext = a.q + (size_t)((s + 1) & 1) * a.q_buf_bytes;
-    const unsigned tag = ((s + 1) >> 1) & 1 ? 0x40u : 0u;  // operand s + 1
+    const unsigned tag = ((s + 1) >> 1) & 1 ? kTag : 0u;  // operand s + 1
     const float rm = a.rtab[m];
 #pragma unroll
     for (int sub = 0; sub < 2; ++sub) {
@@ -426,7 +457,19 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
       if (!alive) break;
       v4f acc[4];
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt) acc[rt] = *reinterpret_cast<const v4f*>(slot + (rt * 64 + lane) * 4);
+      for (int rt = 0; rt < 4; ++rt) {
+        if constexpr (DISC) {
+          typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+          const v2u h = *reinterpret_cast<const v2u*>(slot + (size_t)(rt * 64 + lane) * 8);
+          // the words go through scalars: a bit cast of a vector element expression is
+          // compiled as a cast of element 0 by this compiler
+          const unsigned w0 = h[0], w1 = h[1];
+          const h2 a01 = __builtin_bit_cast(h2, w0), a23 = __builtin_bit_cast(h2, w1);
+          acc[rt] = v4f{(float)a01[0], (float)a01[1], (float)a23[0], (float)a23[1]};
+        } else {
+          acc[rt] = *reinterpret_cast<const v4f*>(slot + (size_t)(rt * 64 + lane) * 16);
+        }
+      }
       __hip_atomic_store(&s_taken[w], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
       after(sub, acc, qnext, tag);
       if (!local) arrive(sub == 0 ? ctr0 : ctr1);
@@ -467,10 +510,10 @@ const void* steps_kernel_ws(int nks, bool discrete) {
   }
 }
 
-size_t steps_ws_lds_bytes(int np) {
+size_t steps_ws_lds_bytes(int np, bool discrete) {
   const int nks = np / kKS;
-  const int nl = nks > kWsRegKSteps ? nks - kWsRegKSteps : 0;
-  return (size_t)16 * nl * 1024 + (size_t)4 * 4 * 64 * 16;
+  const int nl = nks > ws_reg_ksteps(discrete) ? nks - ws_reg_ksteps(discrete) : 0;
+  return (size_t)16 * nl * 1024 + (size_t)4 * ws_slot_bytes(discrete);
 }
 
 }  // namespace gsb
