@@ -92,9 +92,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_counters(name: str):
-    """The committed rocprofv3 counter summary of the step kernel, if it was taken on the
-    current kernel source; else None."""
+def load_counters(name: str, variant: str = HEAD_VARIANT):
+    """The committed rocprofv3 counter summary of a step kernel, if it was taken on the
+    current kernel source and workload; else None."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -103,14 +103,14 @@ def load_counters(name: str):
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_sha256_16") != kernel_source_hash() or d.get("variant") != HEAD_VARIANT:
+    if d.get("kernel_source_sha256_16") != kernel_source_hash() or d.get("variant") != variant:
         return None
     return d
 
 
-def load_traffic(name: str):
-    """HBM bytes per launch of the step kernel (calibrated FETCH_SIZE + WRITE_SIZE)."""
-    d = load_counters(name)
+def load_traffic(name: str, variant: str = HEAD_VARIANT):
+    """HBM bytes per launch of a step kernel (calibrated FETCH_SIZE + WRITE_SIZE)."""
+    d = load_counters(name, variant)
     return None if d is None else d.get("hbm_bytes_per_launch")
 
 
@@ -620,6 +620,7 @@ def main():
                   "roofline": {"bound": "mfma", "achieved": flop / (k16 * 1e-3) / 1e12, "peak": INT8_PEAK / 1e12,
                                "unit": "TOP/s", "frac": flop / (k16 * 1e-3) / INT8_PEAK,
                                "frac_executed": 2 * flop / (k16 * 1e-3) / INT8_PEAK,
+                               "traffic": load_traffic("k_steps_fix16_n2000_r1024_counters.json", "gbsb-fix16"),
                                "note": "frac counts the algorithmic 2 N^2 R M once; the form executes two int8 passes"}}
     _say("fix16 form done")
     # ---- GbSB with the operand rounded to E4M3 (narrower than the paper's JX) ----
