@@ -197,7 +197,6 @@ struct gsb_ctx {
   int chunk_rp = 0;
   int max_wg = 0;  // co-resident workgroups of the step kernel
   int kind = 0;
-  std::vector<float> rtab_host;
   // device memory
   void* ws_user = nullptr;
   size_t ws_user_bytes = 0;
@@ -227,6 +226,10 @@ struct gsb_ctx {
   bool energy_valid = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timed = false;
+  // pinned host staging for gsb_best's small results (copies into pageable memory would
+  // each wait for the device)
+  uint8_t* pinned = nullptr;
+  size_t pinned_bytes = 0;
 };
 
 namespace {
@@ -437,11 +440,12 @@ gsb_status gsb_create(const float* J, const float* h, int32_t n, gsb_ctx** out) 
 void gsb_destroy(gsb_ctx* c) {
   if (!c) return;
   // Teardown cannot report errors; a failed synchronisation or free is ignored here.
-  if (c->ws_own || c->vjp_buf) (void)hipStreamSynchronize(c->stream);
+  (void)hipStreamSynchronize(c->stream);  // also for copies still reading the context's J
   if (c->ws_own) (void)hipFree(c->ws_own);
   if (c->vjp_buf) (void)hipFree(c->vjp_buf);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->pinned) (void)hipHostFree(c->pinned);
   delete c;
 }
 
@@ -570,8 +574,7 @@ namespace {
 // Point the context's buffers into the workspace laid out by `L`, upload and encode J
 // for product form `form` if the workspace does not hold it yet, and write the schedule
 // table r_m = 1 / (M - m) (eqs. (6), (7)), binary64 rounded once.
-gsb_status carve_and_prepare(gsb_ctx* c, const Layout& L, int kind, int form, int schedule, int steps,
-                              bool device_rtab = false) {
+gsb_status carve_and_prepare(gsb_ctx* c, const Layout& L, int kind, int form, int schedule, int steps) {
   uint8_t* b = c->ws;
   const bool j32_moved = reinterpret_cast<float*>(b + L.j32) != c->j32;
   c->j32 = reinterpret_cast<float*>(b + L.j32);
@@ -608,15 +611,9 @@ gsb_status carve_and_prepare(gsb_ctx* c, const Layout& L, int kind, int form, in
     HIP_TRY(launch_encode_j(form, j_fp4, c->j32, c->np, c->jf, c->stream), "encode J");
     c->jf_form = jcode;
   }
-  if (device_rtab) {
-    HIP_TRY(launch_rtab(c->rtab, steps, schedule == GSB_SCHED_LINEAR, c->stream), "schedule table");
-  } else {
-    c->rtab_host.assign(steps, 0.0f);
-    if (schedule == GSB_SCHED_LINEAR)
-      for (int m = 0; m < steps; ++m) c->rtab_host[m] = (float)(1.0 / (double)(steps - m));
-    HIP_TRY(hipMemcpyAsync(c->rtab, c->rtab_host.data(), (size_t)steps * 4, hipMemcpyHostToDevice, c->stream),
-            "upload schedule");
-  }
+  // the schedule table is computed on the device (no host source to keep alive, so a run
+  // needs no synchronisation before its step kernels are queued)
+  HIP_TRY(launch_rtab(c->rtab, steps, schedule == GSB_SCHED_LINEAR, c->stream), "schedule table");
   HIP_TRY(launch_fill_u32(c->status, 64, 0u, c->stream), "clear status");
   return GSB_OK;
 }
@@ -709,9 +706,9 @@ gsb_status gsb_init(gsb_ctx* c, int32_t variant, int32_t schedule, double A, dou
   const int rp = (replicas + kRepPad - 1) / kRepPad * kRepPad;
   s = carve_and_prepare(c, L, kind, form, schedule, steps);
   if (s != GSB_OK) return s;
+  // the only host source of these copies is the context's own J, which lives as long as
+  // the context (gsb_destroy synchronises), so nothing here waits for the device
   HIP_TRY(launch_init_state(c->n, c->np, rp, seed, c->init_mode, c->X, c->Y, c->P, c->stream), "init state");
-  // make the pageable host sources safe to reuse
-  HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronise");
   c->variant = variant;
   c->schedule = schedule;
   c->A = (variant == GSB_GBSB || variant == GSB_GDSB) ? A : 0.0;
@@ -850,7 +847,7 @@ gsb_status gsb_run_noalloc(gsb_ctx* c, int32_t variant, int32_t schedule, double
   } while (0)
   const int form = form_of(c->precision);
   const int rp = (replicas + kRepPad - 1) / kRepPad * kRepPad;
-  s = carve_and_prepare(c, L, kind, form, schedule, steps, /*device_rtab=*/true);
+  s = carve_and_prepare(c, L, kind, form, schedule, steps);
   if (s != GSB_OK) return detach(s);
   c->variant = variant;
   c->schedule = schedule;
@@ -894,14 +891,34 @@ gsb_status gsb_best(gsb_ctx* c, int8_t* spins, double* energy, int32_t* replica)
   if (s != GSB_OK) return s;
   HIP_TRY(launch_best(c->E, c->R, c->best_idx, c->best_e, c->stream), "best kernel");
   HIP_TRY(launch_spins(c->X, c->n_user, c->np, 0, 1, c->anc, c->best_idx, c->spins, c->stream), "spins kernel");
+  // index and energy (adjacent on the device), the status word and the spins go to pinned
+  // staging in one batch of copies and one synchronisation
+  const size_t need = 64 + (size_t)c->n_user;
+  if (c->pinned_bytes < need) {
+    if (c->pinned) {
+      HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronise");
+      HIP_TRY(hipHostFree(c->pinned), "release staging");
+      c->pinned = nullptr;
+      c->pinned_bytes = 0;
+    }
+    void* h = nullptr;
+    if (hipHostMalloc(&h, need, hipHostMallocDefault) != hipSuccess) return fail(GSB_ENOMEM, "pinned staging");
+    c->pinned = static_cast<uint8_t*>(h);
+    c->pinned_bytes = need;
+  }
+  uint8_t* h = c->pinned;
+  HIP_TRY(hipMemcpyAsync(h, c->best_idx, 16, hipMemcpyDeviceToHost, c->stream), "copy best");
+  HIP_TRY(hipMemcpyAsync(h + 16, c->status, 4, hipMemcpyDeviceToHost, c->stream), "status read");
+  if (spins) HIP_TRY(hipMemcpyAsync(h + 64, c->spins, (size_t)c->n_user, hipMemcpyDeviceToHost, c->stream), "copy spins");
+  HIP_TRY(hipStreamSynchronize(c->stream), "stream synchronise");
+  unsigned st = 0;
+  std::memcpy(&st, h + 16, 4);
+  if (st != 0) return fail(GSB_EDEVICE, "step kernel: a replica-group barrier timed out");
   int bi = 0;
   double be = 0;
-  HIP_TRY(hipMemcpyAsync(&bi, c->best_idx, 4, hipMemcpyDeviceToHost, c->stream), "copy best");
-  HIP_TRY(hipMemcpyAsync(&be, c->best_e, 8, hipMemcpyDeviceToHost, c->stream), "copy best");
-  if (spins)
-    HIP_TRY(hipMemcpyAsync(spins, c->spins, (size_t)c->n_user, hipMemcpyDeviceToHost, c->stream), "copy spins");
-  s = check_status_word(c);
-  if (s != GSB_OK) return s;
+  std::memcpy(&bi, h, 4);
+  std::memcpy(&be, h + 8, 8);
+  if (spins) std::memcpy(spins, h + 64, (size_t)c->n_user);
   if (energy) *energy = be;
   if (replica) *replica = bi;
   return GSB_OK;

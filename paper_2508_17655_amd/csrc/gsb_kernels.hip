@@ -1223,35 +1223,42 @@ __global__ void k_energy_final_int(const int* eacc, int r_count, double* E) {
   if (r < r_count) E[r] = -0.5 * (double)eacc[r];
 }
 
-// argmin_r E_r, ties to the lowest r (one workgroup of 256 threads).
+// argmin_r E_r, ties to the lowest r (one workgroup of 256 threads): a strided scan per
+// thread, then a butterfly over the wavefront's 64 lanes with cross-lane shuffles (every
+// lane ends with the wave's minimum), and the four waves' results through LDS.  The
+// order (e, r) is total, so the result does not depend on the reduction order.
+__device__ __forceinline__ bool before_in_order(double e1, int i1, double e2, int i2) {
+  return e1 < e2 || (e1 == e2 && i1 < i2);
+}
 __device__ __forceinline__ void best_of(const double* E, int r_count, int* best_idx, double* best_e, double* se,
                                         int* si) {
   double be = __builtin_inf();
   int bi = 0x7FFFFFFF;
   for (int r = threadIdx.x; r < r_count; r += 256) {
     const double e = E[r];
-    if (e < be || (e == be && r < bi)) { be = e; bi = r; }
+    if (before_in_order(e, r, be, bi)) { be = e; bi = r; }
   }
-  se[threadIdx.x] = be;
-  si[threadIdx.x] = bi;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double e2 = __shfl_xor(be, off, 64);
+    const int i2 = __shfl_xor(bi, off, 64);
+    if (before_in_order(e2, i2, be, bi)) { be = e2; bi = i2; }
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { se[wave] = be; si[wave] = bi; }
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      const double e2 = se[threadIdx.x + w];
-      const int i2 = si[threadIdx.x + w];
-      if (e2 < se[threadIdx.x] || (e2 == se[threadIdx.x] && i2 < si[threadIdx.x])) {
-        se[threadIdx.x] = e2;
-        si[threadIdx.x] = i2;
-      }
-    }
-    __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 1; w < 4; ++w)
+      if (before_in_order(se[w], si[w], be, bi)) { be = se[w]; bi = si[w]; }
+    *best_idx = bi;
+    *best_e = be;
   }
-  if (threadIdx.x == 0) { *best_idx = si[0]; *best_e = se[0]; }
 }
 
 __global__ void __launch_bounds__(256) k_best(const double* E, int r_count, int* best_idx, double* best_e) {
-  __shared__ double se[256];
-  __shared__ int si[256];
+  __shared__ double se[4];
+  __shared__ int si[4];
   best_of(E, r_count, best_idx, best_e, se, si);
 }
 
@@ -1271,8 +1278,8 @@ __global__ void __launch_bounds__(256) k_energy_batch(const StepArgs* inst, cons
 }
 
 __global__ void __launch_bounds__(256) k_energy_best_batch(const BatchInst* bi, int r_count) {
-  __shared__ double se[256];
-  __shared__ int si[256];
+  __shared__ double se[4];
+  __shared__ int si[4];
   const BatchInst& b = bi[blockIdx.x];
   for (int r = threadIdx.x; r < r_count; r += 256) b.E[r] = -0.5 * (double)b.eacc[r];
   __syncthreads();

@@ -464,3 +464,24 @@ def test_field_ancilla_energy(orc):
     ref = orc.energy(J, s) - s.astype(np.float64) @ h.astype(np.float64)
     check_exact(E, ref, "energy with field")
     assert eb == ref.min() and rb == int(np.argmin(ref))
+
+
+@pytest.mark.parametrize("R", [1, 63, 1000])
+def test_best_replica_with_many_ties(orc, R):
+    """gsb_best's argmin (a per-thread scan, a wavefront shuffle butterfly, then the four
+    waves) on a 12-spin instance, where most replicas reach the same few energies: the
+    lowest energy and, among its replicas, the lowest index (numpy's first occurrence)."""
+    n, M = 12, 200
+    say(f"case best-ties n={n} R={R}")
+    J = instances.dense_pm1(n, 31)
+    g = gsb.GSB(J, c=instances.paper_c(n), precision="fp8")
+    g.run("gdsb", A=0.2, dt=1.25, replicas=R, steps=M, seed=5)
+    E = g.energy()
+    s = g.spins()
+    sb, eb, rb = g.best()
+    g.close()
+    check_exact(E, orc.energy(J, s), "energies of the tie case")
+    assert eb == E.min() and rb == int(np.argmin(E))
+    np.testing.assert_array_equal(sb, s[rb])
+    if R == 1000:
+        assert np.sum(E == E.min()) > 1, "the case needs ties at the minimum"
