@@ -722,9 +722,12 @@ def main():
     if not args.no_precision:
         out["precision"] = precision_forms(J, c)
         _say("precision forms done")
-    # this device's measured ceilings (MFMA rates, streaming bandwidths, clock), beside the
-    # published peaks the roofline fractions use
-    ceil = gsb.gsb_device_ceilings()
+    # this device's measured ceilings (MFMA rates, streaming bandwidths, clock, MFMA/VALU
+    # sharing of a SIMD; the measurement library), beside the published peaks the roofline
+    # fractions use
+    from paper_2508_17655_amd import probe
+
+    ceil = probe.device_ceilings()
     ceil["headline_frac_of_measured_fp4xfp8"] = achieved * 1e12 / ceil["mfma_fp4xfp8_flops"]
     out["ceilings"] = ceil
     # L2 reads of the step kernel against this device's measured L2 read rate

@@ -425,21 +425,6 @@ gsb_status gsb_batch_last_ms(gsb_batch* batch, double* ms);
 gsb_status gsb_batch_plan(int32_t units, const int32_t* width, const int32_t* gangs, const double* cost,
                           int32_t queues, int32_t workers, int32_t* queue, int32_t* rank);
 
-/* Measure this device's ceilings, against which the step kernels' roofline fractions can be
- * read (the fractions themselves are stated against the published peaks).  Fills
- * out[0 .. min(count, 13) - 1] with, in order: dense MFMA rate in FLOP/s (OP/s for int8)
- * of the forms the step kernels use -- [0] FP8 x FP8 16x16x128, [1] FP4 x FP8 16x16x128,
- * [2] int8 16x16x64, [3] bf16 16x16x32, [4] binary32 16x16x4 -- from every CU running
- * 4 waves per SIMD of 8 independent MFMA chains; read bandwidth in bytes/s: [5] L2, over
- * 2 MiB with device-scope (L1-skipping) 16-byte loads, four in flight per thread, 8
- * workgroups of 256 threads per CU; streaming over [6] 64 MiB (MALL) and [7] 2 GiB (HBM);
- * [8] streaming write bandwidth over
- * 2 GiB; [9] the shader clock in Hz during a busy kernel (s_memtime against the
- * constant-rate wall clock); then the 32 x 32 MFMA shapes: [10] FP8 x FP8 32x32x64,
- * [11] int8 32x32x32, [12] bf16 32x32x16.  Allocates and frees 2 GiB of device memory; runs on the null
- * stream and synchronises the device.  out: host.  Errors: EINVAL, EDEVICE. */
-gsb_status gsb_device_ceilings(double* out, int32_t count);
-
 /* Encode `count` binary32 values as the operand of the coupling product sum_j J_ij x_j
  * of eq. (3) sees them in precision `precision`, with the encoders the step kernels
  * use for their operand stores.  discrete != 0 encodes the sign s(x) (+1 for x >= 0,

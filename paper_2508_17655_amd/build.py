@@ -1,4 +1,4 @@
-"""Build libgsb.so (gfx950) in-tree with hipcc.
+"""Build libgsb.so (gfx950), and the measurement library libgsb_probe.so, in-tree with hipcc.
 
     python -m paper_2508_17655_amd.build
 """
@@ -11,6 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgsb.so")
+PROBE_LIB = os.path.join(HERE, "libgsb_probe.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -23,7 +24,7 @@ def build(verbose: bool = False) -> str:
     objs = []
     common = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-result"]
     for src, extra in (("gsb_kernels.hip", DEVICE_FLAGS), ("gsb_steps_rj.hip", DEVICE_FLAGS),
-                       ("gsb_steps_ws.hip", DEVICE_FLAGS), ("gsb_probe.hip", DEVICE_FLAGS),
+                       ("gsb_steps_ws.hip", DEVICE_FLAGS),
                        ("gsb_api.cpp", ["-ffp-contract=off"]), ("gsb_batch.cpp", ["-ffp-contract=off"])):
         obj = os.path.join(CSRC, src + ".o")
         cmd = [HIPCC, *common, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
@@ -45,6 +46,19 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     for o in objs:
         os.remove(o)
+    # the device-ceiling probes: a library of their own, not part of the product's
+    obj = os.path.join(CSRC, "gsb_probe.hip.o")
+    tmp = PROBE_LIB + ".tmp"
+    for cmd in ([HIPCC, *common, *DEVICE_FLAGS, "-c", os.path.join(CSRC, "gsb_probe.hip"), "-o", obj],
+                [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", obj, "-o", tmp]):
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("hipcc failed on gsb_probe.hip")
+    os.replace(tmp, PROBE_LIB)
+    os.remove(obj)
     return LIB
 
 

@@ -364,12 +364,6 @@ extern "C" {
 
 const char* gsb_last_error(void) { return g_err.c_str(); }
 
-gsb_status gsb_device_ceilings(double* out, int32_t count) {
-  g_err.clear();
-  if (!out || count < 1) return fail(GSB_EINVAL, "out must hold at least one value");
-  HIP_TRY(measure_ceilings(out, count), "ceiling probes");
-  return GSB_OK;
-}
 gsb_status gsb_encode_operand(int32_t precision, int32_t discrete, const float* x, int64_t count, void* out,
                               void* stream) {
   g_err.clear();

@@ -100,7 +100,8 @@ hipError_t launch_init_batch(const StepArgs* inst, const BatchInst* bi, int coun
                              hipStream_t stream);
 hipError_t launch_energy_batch(const StepArgs* inst, const BatchInst* bi, int count, int np_max, int rp,
                                int r_count, hipStream_t stream);
-// This device's measured ceilings (see gsb_device_ceilings); synchronous, null stream.
+// This device's measured ceilings (gsb_probe.hip, built as its own library); synchronous,
+// null stream.
 hipError_t measure_ceilings(double* out, int count);
 // Message of the last failed C ABI call on this thread (read by gsb_last_error).
 void set_last_error(const char* msg);

@@ -1,6 +1,7 @@
-// gsb_probe.hip -- this device's ceilings, measured: the issue rate of each MFMA form the
-// step kernels use, read bandwidth at L2-, MALL- and HBM-sized footprints, write
-// bandwidth, and the shader clock during a busy kernel.  The roofline fractions of the
+// gsb_probe.hip -- this device's ceilings, measured (libgsb_probe.so, apart from the
+// product library): the issue rate of each MFMA form the step kernels use, how matrix-core
+// and vector-ALU waves share a SIMD, read bandwidth at L2-, MALL- and HBM-sized
+// footprints, write bandwidth, and the shader clock during a busy kernel.  The roofline fractions of the
 // step kernels are stated against the published peaks; these figures say how close to
 // them the chip itself gets.
 #include "gsb_internal.h"
@@ -127,6 +128,61 @@ __global__ void k_clock(int iters, unsigned long long* out, float* sink) {
   if (x == 1.2345e-30f) sink[0] = x;
 }
 
+// Co-issue of the matrix cores and the vector ALU, in the headline kernel's arrangement:
+// 8 waves per workgroup, one workgroup per CU, so each SIMD runs one wave of each kind.
+// Waves 0-3 issue rounds of four independent FP4 x FP8 16x16x128 MFMAs (the product
+// wave's k-step); waves 4-7 issue rounds of 20 binary32 multiplies and adds over ten
+// independent chains (about the update's share of vector instructions per k-step).
+// mode 1: MFMA waves only; 2: VALU waves only; 3: both.
+__global__ void __launch_bounds__(512) k_coissue(int mode, int iters, float* sink) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float s = 0.0f;
+  if (wave < 4) {
+    if (!(mode & 1)) return;
+    const int v = lane * 0x01010101;
+    const v8i b = v8i{v, v + 1, v + 2, v + 3, v + 4, v + 5, v + 6, v + 7} & 0x37373737;
+    const v4i a = v4i{v, v + 1, v + 2, v + 3} & 0x77777777;
+    v4f acc[4] = {};
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(v8i{a[0], a[1], a[2], a[3], a[0], a[1], a[2], a[3]},
+                                                                  b, acc[j], 4, 0, 0, 127, 0, 127);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s += acc[j][0];
+  } else {
+    if (!(mode & 2)) return;
+    float x[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) x[j] = (float)(lane + j) * 1e-3f;
+    const float m = 0.9999f, c = 1e-4f;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int j = 0; j < 10; ++j) x[j] = x[j] * m + c;  // contraction off: a multiply and an add
+    }
+#pragma unroll
+    for (int j = 0; j < 10; ++j) s += x[j];
+  }
+  if (s == 1.2345e-30f) sink[blockIdx.x] = s;
+}
+
+hipError_t time_coissue(int cus, int iters, float* sink, hipEvent_t e0, hipEvent_t e1, double* ms_out) {
+  for (int mode = 1; mode <= 3; ++mode) {
+    hipLaunchKernelGGL(k_coissue, dim3(cus), dim3(512), 0, 0, mode, 1, sink);  // warm-up
+    hipError_t e = hipEventRecord(e0, 0);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_coissue, dim3(cus), dim3(512), 0, 0, mode, iters, sink);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipEventRecord(e1, 0)) != hipSuccess) return e;
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+    float ms = 0;
+    if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return e;
+    ms_out[mode - 1] = ms;
+  }
+  return hipSuccess;
+}
+
 template <int KIND>
 hipError_t time_mfma(int blocks, int iters, float* sink, hipEvent_t e0, hipEvent_t e1, double* rate) {
   hipLaunchKernelGGL(k_mfma_rate<KIND>, dim3(blocks), dim3(256), 0, 0, 1, sink);  // warm-up
@@ -158,7 +214,7 @@ hipError_t measure_ceilings(double* out, int count) {
   if ((e = hipMalloc(&buf, big + sink_floats * 4 + 64)) != hipSuccess) return e;
   float* sink = reinterpret_cast<float*>(static_cast<char*>(buf) + big);
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  double v[13] = {0};
+  double v[16] = {0};
   auto run = [&]() -> hipError_t {
     hipError_t r;
     if ((r = hipEventCreate(&e0)) != hipSuccess) return r;
@@ -172,6 +228,7 @@ hipError_t measure_ceilings(double* out, int count) {
     if ((r = time_mfma<5>(blocks, 1000, sink, e0, e1, &v[10])) != hipSuccess) return r;
     if ((r = time_mfma<6>(blocks, 1000, sink, e0, e1, &v[11])) != hipSuccess) return r;
     if ((r = time_mfma<7>(blocks, 1000, sink, e0, e1, &v[12])) != hipSuccess) return r;
+    if ((r = time_coissue(cus, 20000, sink, e0, e1, &v[13])) != hipSuccess) return r;
     // reads: 2 MiB (each XCD's L2 holds a copy; scattered device-scope loads, above),
     // then streaming over 64 MiB (MALL) and 2 GiB (HBM)
     const v4f* p = static_cast<const v4f*>(buf);
@@ -235,8 +292,13 @@ hipError_t measure_ceilings(double* out, int count) {
   const hipError_t ef = hipFree(buf);
   if (e == hipSuccess) e = ef;
   if (e == hipSuccess)
-    for (int k = 0; k < count && k < 13; ++k) out[k] = v[k];
+    for (int k = 0; k < count && k < 16; ++k) out[k] = v[k];
   return e;
 }
 
 }  // namespace gsb
+
+extern "C" int32_t gsb_probe_ceilings(double* out, int32_t count) {
+  if (!out || count < 0) return (int32_t)hipErrorInvalidValue;
+  return (int32_t)gsb::measure_ceilings(out, count);
+}

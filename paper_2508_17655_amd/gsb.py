@@ -45,7 +45,7 @@ SYMBOLS = ("gsb_create", "gsb_destroy", "gsb_set", "gsb_get", "gsb_set_stream", 
            "gsb_batch_create", "gsb_batch_destroy", "gsb_batch_set_stream", "gsb_batch_workspace_size",
            "gsb_batch_bind_workspace", "gsb_batch_set_coupling", "gsb_batch_set", "gsb_batch_get", "gsb_batch_autotune",
            "gsb_batch_run", "gsb_batch_energy", "gsb_batch_best", "gsb_batch_state", "gsb_batch_last_ms",
-           "gsb_batch_plan", "gsb_device_ceilings", "gsb_encode_operand", "gsb_last_error", "gsb_version")
+           "gsb_batch_plan", "gsb_encode_operand", "gsb_last_error", "gsb_version")
 
 
 class GsbError(RuntimeError):
@@ -113,7 +113,6 @@ def load_library(path: str = LIB_PATH):
         "gsb_batch_state": (i32, [vp, i32, vp, vp, vp]),
         "gsb_batch_last_ms": (i32, [vp, ctypes.POINTER(dbl)]),
         "gsb_batch_plan": (i32, [i32, vp, vp, vp, i32, i32, vp, vp]),
-        "gsb_device_ceilings": (i32, [vp, i32]),
         "gsb_encode_operand": (i32, [i32, i32, vp, ctypes.c_int64, vp, vp]),
         "gsb_last_error": (ctypes.c_char_p, []),
         "gsb_version": (ctypes.c_char_p, []),
@@ -411,17 +410,6 @@ def gsb_batch_plan(width, gangs, cost, queues: int, workers: int):
            "gsb_batch_plan")
     return q, r
 
-
-CEILING_NAMES = ("mfma_fp8_flops", "mfma_fp4xfp8_flops", "mfma_int8_ops", "mfma_bf16_flops", "mfma_fp32_flops",
-                 "read_l2_2MiB_Bps", "read_mall_64MiB_Bps", "read_hbm_2GiB_Bps", "write_hbm_2GiB_Bps", "shader_clock_hz",
-                 "mfma_fp8_32x32_flops", "mfma_int8_32x32_ops", "mfma_bf16_32x32_flops")
-
-
-def gsb_device_ceilings() -> dict:
-    """This device's measured MFMA rates, streaming bandwidths and clock (see gsb.h)."""
-    out = np.zeros(len(CEILING_NAMES), dtype=np.float64)
-    _check(load_library().gsb_device_ceilings(_ptr(out), out.size), "gsb_device_ceilings")
-    return dict(zip(CEILING_NAMES, (float(v) for v in out)))
 
 
 def gsb_encode_operand(precision: int, discrete: int, x_ptr: int | None, count: int, out_ptr: int | None,

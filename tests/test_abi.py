@@ -13,8 +13,8 @@ from paper_2508_17655_amd import gsb, instances
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_symbols():
-    text = open(os.path.join(ROOT, "include", "gsb.h")).read()
+def declared_symbols(header="gsb.h"):
+    text = open(os.path.join(ROOT, "include", header)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(gsb_[a-z_]+)\s*\(", text)))
 
@@ -28,6 +28,17 @@ def test_library_exports_every_declared_symbol():
     for name in declared_symbols():
         assert hasattr(lib, name), name
     assert gsb.gsb_version().startswith("gsb-mi355x")
+
+
+def test_probe_library_is_separate_and_exports_its_header():
+    from paper_2508_17655_amd import probe
+
+    assert declared_symbols("gsb_probe.h") == sorted(probe.SYMBOLS)
+    plib = ctypes.CDLL(probe.LIB_PATH)
+    for name in probe.SYMBOLS:
+        assert hasattr(plib, name), name
+    # the product library carries no measurement code
+    assert not hasattr(ctypes.CDLL(gsb.LIB_PATH), "gsb_probe_ceilings")
 
 
 def _status(fn, *args):

@@ -1,14 +1,15 @@
-"""The device-ceiling probes (gsb_device_ceilings) return rates in the range an MI355X can
-reach: at most the published dense peaks plus a clock margin, and well above zero."""
+"""The device-ceiling probes (libgsb_probe.so, gsb_probe_ceilings) return rates in the range
+an MI355X can reach: at most the published dense peaks plus a clock margin, and well above
+zero; and the MFMA/VALU sharing probe's times are consistent."""
 import pytest
 
 pytestmark = pytest.mark.gpu
 
 
 def test_ceilings_are_plausible():
-    from paper_2508_17655_amd import gsb
+    from paper_2508_17655_amd import probe
 
-    c = gsb.gsb_device_ceilings()
+    c = probe.device_ceilings()
     print(c, flush=True)
     # published dense peaks at 2.4 GHz: FP8 5.0 PFLOP/s, int8 5.0 POP/s, BF16 2.5, FP32 MFMA 0.157
     assert 1.0e15 < c["mfma_fp8_flops"] <= 5.5e15
@@ -21,3 +22,8 @@ def test_ceilings_are_plausible():
     assert 1.0e12 < c["write_hbm_2GiB_Bps"] <= 8.5e12
     assert c["read_l2_2MiB_Bps"] > c["read_hbm_2GiB_Bps"]
     assert 1.0e9 < c["shader_clock_hz"] < 3.0e9
+    # both kinds of waves together take at least as long as either alone and at most the sum
+    # (with a margin for the clock)
+    m, v, b = c["coissue_mfma_only_ms"], c["coissue_valu_only_ms"], c["coissue_both_ms"]
+    assert 0.0 < m and 0.0 < v
+    assert 0.95 * max(m, v) <= b <= 1.1 * (m + v)

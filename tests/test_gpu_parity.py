@@ -162,6 +162,32 @@ def test_full_size_sampled_bitexact(orc, variant):
     check_exact(E, orc.energy(J, spins), "energies")
 
 
+@pytest.mark.parametrize("variant", ["dsb", "gdsb"])
+def test_ferromagnet_largest_sign_products_bitexact(orc, variant):
+    """The largest products the sign kernels hand over: a ferromagnet (J_ij = +1 for all
+    i != j) at n = 2048, one full tile of 16 k-steps, where the spins align within a few
+    steps and |sum_j J_ij s_j| = n - 1 = 2047 (the f16 hand-over holds it exactly)."""
+    n, R, M, A, seed = 2048, 128, 60, 0.2, 77
+    say(f"case ferromagnet variant={variant} n={n} R={R} M={M}")
+    J = np.ones((n, n), dtype=np.float32) - np.eye(n, dtype=np.float32)
+    c = instances.paper_c(n)
+    g = make(J, "fp8", c)
+    g.run(variant, A=A, dt=1.25, replicas=R, steps=M, seed=seed)
+    x, y, p, _ = g.state()
+    E = g.energy()
+    g.close()
+    sample = np.array([0, 77, 127])
+    x0, y0, p0 = oracle_start(orc, n, R, seed, orc.INIT_X)
+    xo, yo, po = orc.run(J, orc.VARIANTS[variant], A=A, dt=1.25, c=c, steps=M, x=x0[sample], y=y0[sample],
+                         p=p0[sample], form=orc.FORM_EXACT, mode="fp32")
+    check_exact(x[sample], xo, "x"); check_exact(y[sample], yo, "y"); check_exact(p[sample], po, "p")
+    s = orc.spins(x)
+    aligned = np.all(s == s[:, :1], axis=1)
+    assert aligned.mean() > 0.9, "the case needs aligned replicas (products of magnitude n - 1)"
+    check_exact(E, orc.energy(J, s), "energies")
+    assert np.all(E[aligned] == -0.5 * n * (n - 1))
+
+
 @pytest.mark.parametrize("variant", ["gbsb", "gdsb"])
 def test_fp8_generic_kernel_bitexact(orc, variant):
     # N_p > 2048: the FP8 product runs in the generic kernel (FP4 J from L2), 2 k-step
