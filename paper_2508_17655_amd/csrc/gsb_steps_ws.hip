@@ -310,18 +310,20 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
           }
           asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]));
           if (ks + kPF < NKS) load_b(sub, cur, ks + kPF, bq[ks % kPF]);
-          if (ks == kTakenAt) taken = __hip_atomic_load(&s_taken[w], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (ks == kTakenAt) taken = __hip_atomic_load(&s_taken[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
           asm volatile("" ::: "memory");
           __builtin_amdgcn_sched_barrier(0);
         }
         if (!alive) break;
         // within one XCD the next operand's first fragments travel during the hand-over
         if (local && has_next) prefetch(sub ^ 1, nbuf);
-        // hand the product to the update wave once it has read the previous one
+        // hand the product to the update wave once it has read the previous one (the
+        // update wave publishes its read count with a release after reading the slot;
+        // LDS operations execute in order, so the relaxed reads here suffice)
         {
           unsigned spins = 0;
           while (taken < seq - 1 &&
-                 (taken = __hip_atomic_load(&s_taken[w], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) < seq - 1) {
+                 (taken = __hip_atomic_load(&s_taken[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) < seq - 1) {
             __builtin_amdgcn_s_sleep(1);
             if (!keep_polling(++spins, kLdsSpinLimit, abort_flag, a.status)) { alive = false; break; }
           }
@@ -338,7 +340,10 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
               *reinterpret_cast<v4f*>(slot + (size_t)(rt * 64 + lane) * 16) = acc[rt];
             }
           }
-          __hip_atomic_store(&s_ready[w], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+          // LDS operations of one wave execute in order, so the flag, written after the
+          // slot, is seen after it; a release here would only wait for the slot writes
+          asm volatile("" ::: "memory");
+          __hip_atomic_store(&s_ready[w], seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         // across XCDs, the operand of the next K loop is loaded behind the group counter
         if (!local) {
