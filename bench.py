@@ -552,7 +552,8 @@ def main():
     if args.profile:
         # as many launches as the default timed run (3 warm-up + 10): the clocks settle
         # over the first few, and the profile's steady mean is then comparable; then the
-        # FIX16 form (GbSB, the paper's JX precision) and the copy kernel
+        # FIX16 form (GbSB, the paper's JX precision), the FP32 and BF16X2 forms, and the
+        # copy kernel
         for s in range(PROFILE_RUNS):
             g8.run(HEAD_VARIANT, A=A_HEAD, dt=DT, replicas=R, steps=M, seed=100 + s)
             g8.best()
@@ -562,9 +563,17 @@ def main():
             g16.run("gbsb", A=A_HEAD, dt=DT, replicas=R, steps=M, seed=200 + s)
             g16.best()
         g16.close()
+        # the other forms' step kernels on the same workload: the FP32 form of the headline
+        # (GdSB, binary32 MFMA) and the BF16X2 form of bSB (continuous product, hi/lo bf16)
+        for form, variant in (("fp32", HEAD_VARIANT), ("bf16x2", "bsb")):
+            gf = gsb.GSB(J, precision=form, c=c)
+            for s in range(3):
+                gf.run(variant, A=A_HEAD, dt=DT, replicas=R, steps=M, seed=400 + s)
+                gf.best()
+            gf.close()
         nbytes = copy_kernel()
         print(json.dumps({"profile_runs": PROFILE_RUNS, "variant": HEAD_VARIANT, "fix16_runs": 5,
-                          "copy_bytes": nbytes}), flush=True)
+                          "fp32_runs": 3, "bf16x2_runs": 3, "copy_bytes": nbytes}), flush=True)
         return
 
     # ---- timed region: the headline form (GdSB, exact FP8 sign product) ----
