@@ -90,6 +90,18 @@ def test_options_and_errors_without_device():
             assert _status(gsb.gsb_set, ctx, gsb.GSB_OPT_GRID_PAD, bad) == gsb.GSB_EINVAL
         gsb.gsb_set(ctx, gsb.GSB_OPT_GRID_PAD, 0)
         assert gsb.gsb_get(ctx, gsb.GSB_OPT_GRID_PAD) == 0
+        # the LLE window start: an integer step >= 0 (gsb_lle checks it against its steps)
+        assert gsb.gsb_get(ctx, gsb.GSB_OPT_LLE_FROM) == 0
+        for bad in (-1, 0.5, float("nan"), float("inf"), 2.0**25):
+            assert _status(gsb.gsb_set, ctx, gsb.GSB_OPT_LLE_FROM, bad) == gsb.GSB_EINVAL
+        gsb.gsb_set(ctx, gsb.GSB_OPT_LLE_FROM, 400)
+        assert gsb.gsb_get(ctx, gsb.GSB_OPT_LLE_FROM) == 400
+        # the device-memory state and reverse-pass calls need a run first (no device work)
+        lib = gsb.load_library()
+        m = ctypes.c_int32()
+        assert lib.gsb_state_device(ctx, None, None, None, ctypes.byref(m)) == gsb.GSB_ESTATE
+        assert lib.gsb_set_state_device(ctx, None, None, None, 0) == gsb.GSB_ESTATE
+        assert lib.gsb_vjp_device(ctx, 1, None, None, None) == gsb.GSB_EINVAL  # NULL cotangents
     finally:
         gsb.gsb_destroy(ctx)
     ctx = gsb.gsb_create(instances.dense_gaussian(10, 2))
