@@ -16,6 +16,9 @@
 #include "gsb_internal.h"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #pragma clang fp contract(off)
@@ -1411,7 +1414,50 @@ int choose_kind(int form, int np, int pref) {
   return pref == 1 ? kKindRegJ : kKindWaveSpec;
 }
 
+// Host-side facts that do not change while the process runs, looked up once: the dynamic
+// LDS attribute of a step kernel on a device, and its co-resident workgroups.
+namespace {
+std::mutex g_host_cache_mu;
+std::map<std::pair<int, const void*>, size_t> g_lds_attr;  // largest dynamic LDS set per kernel
+std::map<std::tuple<int, int, int, int, bool>, int> g_coresident;
+
+// The attribute is a maximum: it is raised when a launch needs more and never lowered, so
+// one kernel launched with several LDS sizes (the generic tiles' J rows scale with n)
+// keeps a setting that covers all of them.
+hipError_t set_lds_attribute_once(const void* k, size_t lds) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(g_host_cache_mu);
+  const auto key = std::make_pair(dev, k);
+  const auto it = g_lds_attr.find(key);
+  if (it != g_lds_attr.end() && it->second >= lds) return hipSuccess;
+  e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess) g_lds_attr[key] = lds;
+  return e;
+}
+}  // namespace
+
+static int coresident_uncached(int form, int kind, int np, bool tangent);
+
 int max_coresident_workgroups(int form, int kind, int np, bool tangent) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  const auto key = std::make_tuple(dev, form, kind, np, tangent);
+  {
+    std::lock_guard<std::mutex> lock(g_host_cache_mu);
+    const auto it = g_coresident.find(key);
+    if (it != g_coresident.end()) return it->second;
+  }
+  const int v = coresident_uncached(form, kind, np, tangent);
+  if (v > 0) {
+    std::lock_guard<std::mutex> lock(g_host_cache_mu);
+    g_coresident[key] = v;
+  }
+  return v;
+}
+
+static int coresident_uncached(int form, int kind, int np, bool tangent) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
@@ -1425,8 +1471,7 @@ int max_coresident_workgroups(int form, int kind, int np, bool tangent) {
     const void* k = steps_kernel_for(form, kind, np, disc != 0);
     if (!k) return 0;
     const size_t lds = steps_lds_bytes(form, kind, np, disc != 0);
-    if (lds > 0 && hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-      return 0;
+    if (lds > 0 && set_lds_attribute_once(k, lds) != hipSuccess) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads_kind(kind), lds) != hipSuccess) return 0;
     best = disc == 0 ? per_cu * cus : std::min(best, per_cu * cus);
   }
@@ -1457,7 +1502,7 @@ hipError_t launch_steps(int form, int kind, const StepArgs& a, hipStream_t strea
   if (!k) return hipErrorInvalidValue;
   const size_t lds = steps_lds_bytes(form, kind, a.np, a.discrete != 0);
   if (lds > 0) {
-    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const hipError_t e = set_lds_attribute_once(k, lds);
     if (e != hipSuccess) return e;
   }
   StepArgs copy = a;
