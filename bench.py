@@ -325,9 +325,23 @@ def chaos_sweeps(J, c):
     d_grid, ms_grid = delta_at(grid, T)
     d_sweep, ms_sweep = delta_at([0.0] + A_SWEEP, M)
     gp.close()
+
+    def edge(values):
+        """The A beyond which the window estimate stays positive: the last sign change from
+        <= 0 to > 0 over the grid, interpolated linearly in ln A (None if it never turns)."""
+        last = None
+        for k in range(1, len(grid)):
+            v0, v1 = values[k - 1], values[k]
+            if v0 is not None and v1 is not None and v0 <= 0.0 < v1:
+                t = v0 / (v0 - v1)
+                last = math.exp(math.log(grid[k - 1]) + t * (math.log(grid[k]) - math.log(grid[k - 1])))
+        if last is None or any(v is None or v <= 0.0 for v in values[grid.index(min(g for g in grid if g >= last)):]):
+            return None
+        return last
     return {"A": grid, "n": N, "steps": T, "dt": DT, "form": "fp32 (primal and tangent)",
             "lle": {"replicas_per_A": per, "renorm_every": renorm, "whole_run": est["whole"],
                     "post_bifurcation": est["window"],
+                    "edge_of_chaos_A": edge(est["window"]["mean"]),
                     "vanished": "replicas whose every tangent component reached a wall (estimate -inf)"},
             "delta": {"mean": d_grid, "pairs": pairs, "ms": ms_grid, "chaos_level": 1.0 / math.sqrt(2.0)},
             "delta_success_schedule": {"A": [0.0] + A_SWEEP, "steps": M, "mean": d_sweep, "pairs": pairs,
