@@ -98,17 +98,24 @@ __device__ __forceinline__ bool group_sync(unsigned* ctr, unsigned target, int l
 __device__ __forceinline__ float operand_value(float x, bool discrete) {
   return discrete ? (x < 0.0f ? -1.0f : 1.0f) : x;
 }
-// FP8: OCP E4M3 bytes, value v in byte v (round to nearest even, the hardware conversion).
+// FP8: OCP E4M3 bytes, value v in byte v (round to nearest even, the hardware conversion),
+// with `orin` ORed into the word (the step tag of the step kernels).
 template <bool DISC>
-__device__ __forceinline__ unsigned encode_fp8x4(const float xv[4]) {
+__device__ __forceinline__ unsigned encode_fp8x4(const float xv[4], unsigned orin = 0u) {
   if constexpr (DISC) {
-    unsigned w = 0x38383838u;  // +1.0 in E4M3 in every byte, sign bits from x
-    w |= (xv[0] < 0.0f ? 0x80u : 0u) | (xv[1] < 0.0f ? 0x8000u : 0u) | (xv[2] < 0.0f ? 0x800000u : 0u) |
-         (xv[3] < 0.0f ? 0x80000000u : 0u);
-    return w;
+    // +1.0 in E4M3 (0x38) in every byte, with the sign bit of the E4M3 conversion of
+    // x + 0: adding +0 turns -0.0 into +0.0 and leaves every other value as it is, and the
+    // conversion keeps the sign (a value that rounds to zero gives a signed zero), so the
+    // bit is set exactly where x < 0.  bitop3 0xEA: (a & b) | c.  The first conversion
+    // writes the low half of a register that starts as any value at hand (here n0, which
+    // it reads first; the second conversion replaces the high half).
+    const float n0 = xv[0] + 0.0f;
+    const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(n0, xv[1] + 0.0f, __builtin_bit_cast(int, n0), false);
+    const int w = __builtin_amdgcn_cvt_pk_fp8_f32(xv[2] + 0.0f, xv[3] + 0.0f, lo, true);
+    return __builtin_amdgcn_bitop3_b32((unsigned)w, 0x80808080u, 0x38383838u | orin, 0xEA);
   } else {
-    int lo = __builtin_amdgcn_cvt_pk_fp8_f32(xv[0], xv[1], 0, false);
-    return (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(xv[2], xv[3], lo, true);
+    const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(xv[0], xv[1], 0, false);
+    return (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(xv[2], xv[3], lo, true) | orin;
   }
 }
 // BF16X2: hi = bf16(q), lo = bf16(q - hi) (q - hi is exact in binary32); two bf16 per word.
@@ -143,6 +150,16 @@ __device__ __forceinline__ void encode_fix16x4(const float xv[4], unsigned& wh, 
   }
 }
 
+// Byte offset, within one operand buffer, of the FP8 word of a lane's four rows (16x16
+// tile origin ibase, rcol): fragments of 16 replicas x 128 spins, split in two 1 KiB halves
+// of 64 lanes x 16 spins.
+__device__ __forceinline__ size_t fp8_operand_offset(int nks, int ibase, int rcol, int lane) {
+  const int kk0 = (ibase & 127) + 4 * (lane >> 4);  // first of this lane's 4 rows
+  const int lanep = (lane & 15) + 16 * (kk0 >> 5);
+  const int half = (kk0 & 31) >> 4;
+  return ((size_t)((rcol >> 4) * nks + (ibase >> 7)) * 2 + half) * 1024 + lanep * 16 + (kk0 & 15);
+}
+
 // fp8_tag (FP8 only) is ORed into the stored word: a step tag in bit 6 of its first byte,
 // which the E4M3 code of any |x| <= 1 leaves clear (exponent field at most 7).
 template <int FORM, bool DISC>
@@ -153,11 +170,11 @@ __device__ __forceinline__ void store_operand(uint8_t* qbuf, size_t plane_bytes,
   const int kc = ibase >> 7;
   const int kk0 = (ibase & 127) + 4 * (lane >> 4);  // first of this lane's 4 rows
   if constexpr (FORM == kFormFP8) {
-    const unsigned w = encode_fp8x4<DISC>(xv) | fp8_tag;
-    const int lanep = (lane & 15) + 16 * (kk0 >> 5);
-    const int half = (kk0 & 31) >> 4;
-    const size_t off = ((size_t)(rb * nks + kc) * 2 + half) * 1024 + lanep * 16 + (kk0 & 15);
-    *reinterpret_cast<unsigned*>(qbuf + off) = w;
+    const unsigned w = encode_fp8x4<DISC>(xv, fp8_tag);
+    (void)kk0;
+    (void)rb;
+    (void)kc;
+    *reinterpret_cast<unsigned*>(qbuf + fp8_operand_offset(nks, ibase, rcol, lane)) = w;
   } else if constexpr (FORM == kFormBF16X2) {
     v2u wh, wl;
     encode_bf16x4<DISC>(xv, wh, wl);

@@ -59,6 +59,22 @@ __device__ __forceinline__ bool keep_polling(unsigned spins, unsigned limit, uns
   return true;
 }
 
+// c * h for the f16 h in the low (HI false) or high half of word hw, in one instruction:
+// a fused multiply-add with addend -0.0 (the product of a binary32 and an f16 is exact
+// before its one rounding, and x + -0.0 = x for every x, zeros included) gives the
+// binary32 product c * (float)h bit for bit, without converting h first.  The compiler
+// folds a written fmaf(c, h, -0.0f) into a multiply after the conversion, hence the asm
+// (register operands only, no memory access).
+template <bool HI>
+__device__ __forceinline__ float mul_f16(float c, unsigned hw, float nz) {
+  float d;
+  if constexpr (HI)
+    asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel:[0,1,0] op_sel_hi:[0,1,0]" : "=v"(d) : "s"(c), "v"(hw), "v"(nz));
+  else
+    asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel:[0,0,0] op_sel_hi:[0,1,0]" : "=v"(d) : "s"(c), "v"(hw), "v"(nz));
+  return d;
+}
+
 template <int NKS, bool DISC>
 __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
@@ -408,10 +424,17 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) t[e] = ys[sub][e >> 2][e & 3] - t[e];            // y + dy
   };
-  auto after = [&](int sub, const v4f* acc, uint8_t* qnext, unsigned tag) {
-    float u[16];
+  // the operand buffers as one buffer resource; this lane's word of row tile rt of column
+  // tile sub sits at qoff[sub][rt] in either buffer
+  const __amdgpu_buffer_rsrc_t qw = make_rsrc(a.q, 2 * a.q_buf_bytes);
+  unsigned qoff[2][4];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) u[e] = cdt * acc[e >> 2][e & 3];                 // Dy
+  for (int sub = 0; sub < 2; ++sub)
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+      qoff[sub][rt] = (unsigned)fp8_operand_offset(NKS, row0 + rt * 16, col0 + sub * 16, lane);
+  // u holds Dy = c dt (J q)_i of the lane's 16 elements on entry
+  auto after = [&](int sub, float* u, int qbase, unsigned tag) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) t[e] = t[e] + u[e];                              // eq. (3)
 #pragma unroll
@@ -425,8 +448,7 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
     }
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt)
-      store_operand<kFormFP8, DISC>(qnext, a.q_buf_bytes, NKS, row0 + rt * 16, col0 + sub * 16, lane,
-                                    xs[sub][rt], tag);
+      __builtin_amdgcn_raw_buffer_store_b32(encode_fp8x4<DISC>(xs[sub][rt], tag), qw, qoff[sub][rt], qbase, 0);
   };
 
   // the step tag: bit 6 of the word's first byte, or of every byte for the sign operand
@@ -448,7 +470,7 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
   }
   for (int s = 0; alive && s < steps; ++s) {
     const int m = a.m_begin + s;
-    uint8_t* qnext = a.q + (size_t)((s + 1) & 1) * a.q_buf_bytes;
+    const int qbase = ((s + 1) & 1) * (int)a.q_buf_bytes;  // operand s + 1 in buffer (s + 1) % 2
     const unsigned tag = ((s + 1) >> 1) & 1 ? kTag : 0u;  // operand s + 1
     const float rm = a.rtab[m];
 #pragma unroll
@@ -460,23 +482,26 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
         if (!keep_polling(++spins, kLdsSpinLimit, abort_flag, a.status)) { alive = false; break; }
       }
       if (!alive) break;
-      v4f acc[4];
+      float u[16];  // Dy = c dt (J q)_i, eq. (3)
 #pragma unroll
       for (int rt = 0; rt < 4; ++rt) {
         if constexpr (DISC) {
-          typedef _Float16 h2 __attribute__((ext_vector_type(2)));
           const v2u h = *reinterpret_cast<const v2u*>(slot + (size_t)(rt * 64 + lane) * 8);
           // the words go through scalars: a bit cast of a vector element expression is
           // compiled as a cast of element 0 by this compiler
           const unsigned w0 = h[0], w1 = h[1];
-          const h2 a01 = __builtin_bit_cast(h2, w0), a23 = __builtin_bit_cast(h2, w1);
-          acc[rt] = v4f{(float)a01[0], (float)a01[1], (float)a23[0], (float)a23[1]};
+          u[4 * rt + 0] = mul_f16<false>(cdt, w0, -0.0f);
+          u[4 * rt + 1] = mul_f16<true>(cdt, w0, -0.0f);
+          u[4 * rt + 2] = mul_f16<false>(cdt, w1, -0.0f);
+          u[4 * rt + 3] = mul_f16<true>(cdt, w1, -0.0f);
         } else {
-          acc[rt] = *reinterpret_cast<const v4f*>(slot + (size_t)(rt * 64 + lane) * 16);
+          const v4f acc = *reinterpret_cast<const v4f*>(slot + (size_t)(rt * 64 + lane) * 16);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) u[4 * rt + v] = cdt * acc[v];
         }
       }
       __hip_atomic_store(&s_taken[w], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-      after(sub, acc, qnext, tag);
+      after(sub, u, qbase, tag);
       if (!local) arrive(sub == 0 ? ctr0 : ctr1);
     }
   }
