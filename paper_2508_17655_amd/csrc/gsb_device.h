@@ -150,14 +150,25 @@ __device__ __forceinline__ void encode_fix16x4(const float xv[4], unsigned& wh, 
   }
 }
 
-// Byte offset, within one operand buffer, of the FP8 word of a lane's four rows (16x16
-// tile origin ibase, rcol): fragments of 16 replicas x 128 spins, split in two 1 KiB halves
-// of 64 lanes x 16 spins.
+// FP8 operand placement.  A fragment (16 replicas x one 128-spin k-step) is two 1 KiB
+// halves of 64 lanes x 16 bytes, the B operand of the 16x16x128 MFMA: lane p of a half
+// holds replica p mod 16 and lane group g = p / 16, byte j of the lane's 32 (16 h + b for
+// half h) is MFMA k index 16 g + b + 64 h.  Which spin feeds which k index is free as long
+// as J (below) uses the same map; this one puts spin kk = k mod 128 at
+//   half kk / 64, lane group (kk / 4) mod 4, byte 4 ((kk / 16) mod 4) + kk mod 4,
+// so that the sixteen spins 64 h + 16 t + 4 L + v (t, v < 4) of one replica -- the four
+// row tiles t of lane L of a 16x16 MFMA result, rows 4 L + v -- are one lane's 16
+// contiguous bytes, which the lane that computed them can store with wide stores.
+__device__ __forceinline__ size_t fp8_elem_offset(int nks, int r, int k) {
+  const int kk = k & 127;
+  const int lanep = (r & 15) + 16 * ((kk >> 2) & 3);
+  return ((size_t)((r >> 4) * nks + (k >> 7)) * 2 + (kk >> 6)) * 1024 + lanep * 16 + (((kk >> 4) & 3) << 2) +
+         (kk & 3);
+}
+// Offset of the FP8 word of a lane's four rows (16x16 tile origin ibase, rcol; rows
+// ibase + 4 (lane / 16) + v, replica rcol + lane mod 16): bytes v of one word.
 __device__ __forceinline__ size_t fp8_operand_offset(int nks, int ibase, int rcol, int lane) {
-  const int kk0 = (ibase & 127) + 4 * (lane >> 4);  // first of this lane's 4 rows
-  const int lanep = (lane & 15) + 16 * (kk0 >> 5);
-  const int half = (kk0 & 31) >> 4;
-  return ((size_t)((rcol >> 4) * nks + (ibase >> 7)) * 2 + half) * 1024 + lanep * 16 + (kk0 & 15);
+  return fp8_elem_offset(nks, rcol + (lane & 15), ibase + 4 * (lane >> 4));
 }
 
 // fp8_tag (FP8 only) is ORed into the stored word: a step tag in bit 6 of its first byte,
@@ -206,15 +217,14 @@ __device__ __forceinline__ void store_operand(uint8_t* qbuf, size_t plane_bytes,
   }
 }
 
-// J (zero padded, entries in {0, +-1}) -> FP4 (E2M1) fragment-major layout of the
-// register-resident FP8 path: [row tile][k-step][lane 64][16 bytes], two values per byte,
-// low nibble first.  In the mixed FP4 x FP8 MFMA (16x16x128), FP8 byte j of lane group g
-// multiplies FP4 nibble p of the same row/column lanes with p = 16 g + j for j < 16 and
-// p = 64 + 16 g + (j - 16) for j >= 16 (p counts nibbles over the four lane groups,
-// 32 per group).  The FP8 operand layout puts k-step offset kk = 32 g + j at byte j of
-// lane group g, so nibble p must hold kk(p) below.
+// J (zero padded, entries in {0, +-1}) -> FP4 (E2M1) fragment-major layout of the FP8
+// product: [row tile][k-step][lane 64][16 bytes], two values per byte, low nibble first.
+// In the mixed FP4 x FP8 MFMA (16x16x128), FP4 nibble p (0..127 over the four lane groups
+// of a row tile, 32 per group) multiplies MFMA k index p of the operand, which is FP8 byte
+// j = p mod 16 of lane group (p mod 64) / 16 in half p / 64; the spin there is the one the
+// operand placement (fp8_elem_offset) puts at that byte.
 __device__ __forceinline__ int fp4_pair_kk(int p) {
-  return p < 64 ? 32 * (p >> 4) + (p & 15) : 32 * ((p - 64) >> 4) + 16 + ((p - 64) & 15);
+  return 64 * (p >> 6) + 16 * ((p >> 2) & 3) + 4 * ((p >> 4) & 3) + (p & 3);
 }
 __device__ __forceinline__ unsigned fp4_code(float v) {  // exact for 0 and +-1
   return (v < 0.0f ? 0x8u : 0u) | (__builtin_fabsf(v) == 1.0f ? 0x2u : 0u);

@@ -858,10 +858,8 @@ __global__ void k_encode_j(const float* j32, int np, uint8_t* jf) {
     const int i = (int)(t / np), k = (int)(t % np);
     const float v = j32[t];
     const int rt = i >> 4, kc = k >> 7, kk = k & 127;
-    if constexpr (FORM == kFormFP8) {
-      const int lanep = (i & 15) + 16 * (kk >> 5);
-      const size_t off = ((size_t)(rt * nks + kc) * 2 + ((kk & 31) >> 4)) * 1024 + lanep * 16 + (kk & 15);
-      jf[off] = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xFF);
+    if constexpr (FORM == kFormFP8) {  // E4M3 J: the operand's placement, row i for replica r
+      jf[fp8_elem_offset(nks, i, k)] = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xFF);
     } else if constexpr (FORM == kFormFIX16) {  // int8 J (entries in {0, +-1}), 32x32x32 A layout
       const int lanep = (i & 31) + 32 * ((kk & 31) >> 4);
       const size_t off = ((size_t)((i >> 5) * nks + kc) * 4 + (kk >> 5)) * 1024 + lanep * 16 + (kk & 15);
@@ -1157,13 +1155,9 @@ __device__ __forceinline__ void sign_fp8_elems(const float* x, int np, int nks, 
   for (size_t t = t0; t < quads; t += stride) {
     const int r = (int)((t * 4) / np), k = (int)((t * 4) % np);
     const v4f v = *reinterpret_cast<const v4f*>(x + (size_t)r * np + k);
-    unsigned w = 0x38383838u;  // +1.0 in every byte
-    w |= (v[0] < 0.0f ? 0x80u : 0u) | (v[1] < 0.0f ? 0x8000u : 0u) | (v[2] < 0.0f ? 0x800000u : 0u) |
-         (v[3] < 0.0f ? 0x80000000u : 0u);
-    const int kc = k >> 7, kk = k & 127;
-    const int lanep = (r & 15) + 16 * (kk >> 5);
-    const size_t off = ((size_t)((r >> 4) * nks + kc) * 2 + ((kk & 31) >> 4)) * 1024 + lanep * 16 + (kk & 15);
-    *reinterpret_cast<unsigned*>(s8 + off) = w;
+    const float xv[4] = {v[0], v[1], v[2], v[3]};
+    // spins k..k+3 (k a multiple of 4) are four consecutive bytes of the placement
+    *reinterpret_cast<unsigned*>(s8 + fp8_elem_offset(nks, r, k)) = encode_fp8x4<true>(xv);
   }
 }
 

@@ -17,11 +17,13 @@
 // of its first byte (the E4M3 code of a value in [-1, 1] never sets that bit; the wall of
 // eq. (5) keeps x there).  Operand k (k = 0 at the launch's first step) sits in buffer
 // k % 2 with tag (k / 2) % 2, so a buffer holds either the operand a product wave wants or
-// the one two steps older, whose tag differs.  Each product wave strips and checks the tag
-// of every word it loads and loads again while any is stale (the sign operand of dSB and
-// GdSB carries the tag in every byte and is not stripped: tagged, its bytes are +-256
-// instead of +-1, which the MFMA's E8M0 block scale of 2^-8 undoes exactly): a word is written by one
-// 32-bit store and so is seen whole or not at all, and no group counter is needed between
+// the one two steps older, whose tag differs.  The update waves write the operand in
+// aligned 64-bit units, two words of one lane per store (the operand placement keeps a
+// lane's rows together), and an aligned 64-bit store is seen whole or not at all; each
+// product wave strips the tag of every word it loads, checks one word per unit and loads
+// again while any is stale (the sign operand of dSB and GdSB carries the tag in every
+// byte and is not stripped: tagged, its bytes are +-256 instead of +-1, which the MFMA's
+// E8M0 block scale of 2^-8 undoes exactly), and no group counter is needed between
 // steps.  The launch's first operand is behind the group counter (buffer 1 is cleared to
 // the stale tag under the same counter).  Where the group spans XCDs, whose L2 caches are
 // not coherent with each other, every step also goes through the group counter with
@@ -198,21 +200,22 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
     };
     // strip the step tag from fragments and report (for the whole wave) whether any of
     // their words was stale: pat is the expected tag, cmask 0x40 (or 0: no check).  The
-    // sign product keeps its tags: there the tag is in every byte of a word, a tagged +-1
-    // byte is +-256 exactly, and the MFMA's block scale of the operand (2^-8 for a tagged
-    // operand) takes the factor back exactly, so the words are only checked.
+    // update waves write the operand in aligned 64-bit units (two words of one lane, one
+    // store), so one word of each unit tells its step: words 0, 2, 4, 6 of the fragment.
+    // The sign product keeps its tags: there the tag is in every byte of a word, a tagged
+    // +-1 byte is +-256 exactly, and the MFMA's block scale of the operand (2^-8 for a
+    // tagged operand) takes the factor back exactly, so the words are only checked.
     auto strip = [&](v8i& b, unsigned pat) -> unsigned {
       unsigned o = 0;
       if constexpr (DISC) {
-        // (b0 ^ pat) | (b1 ^ pat) per pair of words: one bitop3 each (truth table 0x7E)
-#pragma unroll
-        for (int d = 0; d < 8; d += 2)
-          o |= __builtin_amdgcn_bitop3_b32((unsigned)b[d], (unsigned)b[d + 1], pat, 0x7E);
+        // (b0 ^ pat) | (b2 ^ pat), (b4 ^ pat) | (b6 ^ pat): one bitop3 each (table 0x7E)
+        o = __builtin_amdgcn_bitop3_b32((unsigned)b[0], (unsigned)b[2], pat, 0x7E) |
+            __builtin_amdgcn_bitop3_b32((unsigned)b[4], (unsigned)b[6], pat, 0x7E);
       } else {
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
           b[d] ^= (int)pat;
-          o |= (unsigned)b[d];
+          if (d % 2 == 0) o |= (unsigned)b[d];
         }
       }
       return o;
@@ -424,15 +427,13 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) t[e] = ys[sub][e >> 2][e & 3] - t[e];            // y + dy
   };
-  // the operand buffers as one buffer resource; this lane's word of row tile rt of column
-  // tile sub sits at qoff[sub][rt] in either buffer
+  // the operand buffers as one buffer resource; this lane's words of column tile sub sit
+  // at qoff[sub] in either buffer, those of row tiles 0..3 one after the other (the
+  // placement keeps a lane's sixteen spins of a k-step together; row0 is a multiple of 64)
   const __amdgpu_buffer_rsrc_t qw = make_rsrc(a.q, 2 * a.q_buf_bytes);
-  unsigned qoff[2][4];
+  unsigned qoff[2];
 #pragma unroll
-  for (int sub = 0; sub < 2; ++sub)
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-      qoff[sub][rt] = (unsigned)fp8_operand_offset(NKS, row0 + rt * 16, col0 + sub * 16, lane);
+  for (int sub = 0; sub < 2; ++sub) qoff[sub] = (unsigned)fp8_operand_offset(NKS, row0, col0 + sub * 16, lane);
   // u holds Dy = c dt (J q)_i of the lane's 16 elements on entry
   auto after = [&](int sub, float* u, int qbase, unsigned tag) {
 #pragma unroll
@@ -446,9 +447,13 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
       ys[sub][e >> 2][e & 3] = __builtin_fabsf(u[e]) > 1.0f ? 0.0f : t[e];
       xs[sub][e >> 2][e & 3] = __builtin_amdgcn_fmed3f(u[e], -1.0f, 1.0f);
     }
+    // row tiles 2 h and 2 h + 1 in one 64-bit store: the product waves check one word of
+    // each aligned 64-bit unit (an aligned 64-bit store is seen whole or not at all)
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-      __builtin_amdgcn_raw_buffer_store_b32(encode_fp8x4<DISC>(xs[sub][rt], tag), qw, qoff[sub][rt], qbase, 0);
+    for (int h = 0; h < 2; ++h) {
+      const v2u wd{encode_fp8x4<DISC>(xs[sub][2 * h], tag), encode_fp8x4<DISC>(xs[sub][2 * h + 1], tag)};
+      __builtin_amdgcn_raw_buffer_store_b64(wd, qw, qoff[sub] + 8 * h, qbase, 0);
+    }
   };
 
   // the step tag: bit 6 of the word's first byte, or of every byte for the sign operand
