@@ -308,6 +308,10 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
         v4f acc[4];
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) acc[rt] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+        // the scale in a vector register of its own for the whole K loop (as a scalar the
+        // compiler copies it into a free vector register before every k-step)
+        int scale_v;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(scale_v) : "s"(scale_q));
         v4i jl[2][4];
         if constexpr (NL > 0) load_jl(NR, jl[0]);
 #pragma unroll
@@ -325,7 +329,7 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
           for (int rt = 0; rt < 4; ++rt) {
             const v4i f = ks < NR ? jr[rt][ks < NR ? ks : 0] : jl[(ks - NR) & 1][rt];
             acc[rt] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(cat(f, f), bq[ks % kPF], acc[rt], 4, 0, 0,
-                                                                       127, 0, scale_q);
+                                                                       127, 0, scale_v);
           }
           asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]));
           if (ks + kPF < NKS) load_b(sub, cur, ks + kPF, bq[ks % kPF]);
