@@ -399,7 +399,7 @@ def batched_uneven(seed: int = 1):
         graph_ms.append(b.last_ms())
     e_best, _ = b.best()
     ns = np.array([s_[1] for s_ in specs], dtype=np.float64)
-    nps = np.ceil(ns / 512) * 512
+    nps = np.ceil(ns / 256) * 256  # the batch pads each instance to 256 spins
     tiles = np.array([b.get(k, gsb.GSB_BATCH_TILE_ROWS) for k in range(count)])
     us = np.array([b.get(k, gsb.GSB_BATCH_STEP_US) for k in range(count)])
     grid = b.get(-1, gsb.GSB_BATCH_GRID)

@@ -446,7 +446,7 @@ gsb_status gsb_batch_create(int32_t count, const int32_t* n, int32_t replicas, g
     b->n.assign(n, n + count);
     b->np.resize(count);
     for (int k = 0; k < count; ++k) {
-      b->np[k] = (n[k] + kRowPad - 1) / kRowPad * kRowPad;
+      b->np[k] = (n[k] + kBatchRowPad - 1) / kBatchRowPad * kBatchRowPad;
       b->np_max = std::max(b->np_max, b->np[k]);
     }
     b->c.assign(count, 0.0);

@@ -153,7 +153,7 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
   } else if constexpr (LJ) {
     {
       constexpr int kTilesWG = BM / 16;
-      nks_l = min(nks, lds_bytes / (kTilesWG * 1024)) / kKStepsUnroll * kKStepsUnroll;
+      nks_l = min(nks, lds_bytes / (kTilesWG * 1024)) / QD * QD;  // whole pipeline rounds
       const uint8_t* jwg = static_cast<const uint8_t*>(a.jf) + (size_t)(mb * kTilesWG) * nks * 1024;
       const int chunks = kTilesWG * nks_l * 64;
       for (int c = tid; c < chunks; c += kThreads) {
@@ -222,10 +222,11 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
       // MFMA stream.  The k-steps run in two segments, [0, nks_l) with J from LDS and
       // [nks_l, nks) with J from L2, each a pipeline of its own: J registers are then
       // never written by an LDS read while a global load to them may be in flight (which
-      // would force a full wait).  Segment lengths are multiples of kPF; the last kPF
-      // k-steps of each are peeled without Q loads.
+      // would force a full wait).  The pipelined part of a segment is a multiple of kPF
+      // k-steps (any remainder runs first, unpipelined); its last kPF k-steps are peeled
+      // without Q loads.
       constexpr int kPF = QD;
-      static_assert(kKStepsUnroll % kPF == 0, "segments are multiples of kKStepsUnroll");
+      static_assert(kKStepsUnroll % kPF == 0, "a pipeline round divides the single-instance padding");
       v8i bq[kPF][2];
       auto load_b = [&](int ks, v8i* dst) {
 #pragma unroll
@@ -284,10 +285,23 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
           __builtin_amdgcn_sched_barrier(0);
         }
       };
+      // A segment whose length is not a multiple of kPF (a batched instance padded to two
+      // k-steps, in the one-workgroup-per-CU variant) runs its first (k1 - k0) mod kPF
+      // k-steps without a pipeline, before the pipeline's prologue.
+      auto run_segment = [&](int k0, int k1, auto load_a, auto jd) {
+        const int r = (k1 - k0) % kPF;
+        for (int ks = k0; ks < k0 + r; ++ks) {
+          v4i aa[4];
+          load_b(ks, bq[0]);
+          load_a(ks, aa);
+          mfmas(aa, bq[0]);
+        }
+        if (k1 - k0 - r > 0) segment(k0 + r, k1, load_a, jd);
+      };
       if constexpr (LJ) {
-        if (nks_l > 0) segment(0, nks_l, load_a_lds, std::integral_constant<int, 1>{});
+        if (nks_l > 0) run_segment(0, nks_l, load_a_lds, std::integral_constant<int, 1>{});
       }
-      if (nks_l < nks) segment(nks_l, nks, load_a_glb, std::integral_constant<int, kPF - 1>{});
+      if (nks_l < nks) run_segment(nks_l, nks, load_a_glb, std::integral_constant<int, kPF - 1>{});
     } else if constexpr (FORM == kFormBF16X2) {
       // hi and lo planes of x (the sign operand has no low part) against bf16 J on
       // 32x32x16 MFMAs (the 16x16x32 shape runs at ~55% of their rate here), binary32
@@ -595,8 +609,17 @@ __device__ __forceinline__ uint64_t ufirst64(uint64_t v) {
   const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
   return ((uint64_t)hi << 32) | lo;
 }
+// Every pointer of the table points to device memory.  Rebuilt from an integer, a pointer
+// is generic to the compiler, and generic (flat) accesses count against the LDS counter as
+// well as the memory counter and may complete out of order with other memory accesses, so
+// every wait for one drains all outstanding loads; a global-address-space pointer cast to
+// a generic one lets the compiler's address-space inference make them global accesses.
 template <class T>
-__device__ __forceinline__ T* ufirst(T* p) { return reinterpret_cast<T*>(ufirst64(reinterpret_cast<uint64_t>(p))); }
+__device__ __forceinline__ T* ufirst(T* p) {
+  typedef __attribute__((address_space(1))) T GT;
+  GT* g = (GT*)ufirst64(reinterpret_cast<uint64_t>(p));
+  return (T*)g;
+}
 
 __device__ __forceinline__ StepArgs uniform_args(const StepArgs& a) {
   StepArgs u;

@@ -16,6 +16,9 @@ constexpr int kKS = 128;       // K (spins j) per k-step
 constexpr int kThreads = 256;
 constexpr int kKStepsUnroll = 4;  // k-steps per software-pipeline round
 constexpr int kRowPad = kKS * kKStepsUnroll;  // np is a multiple of this (512)
+// batched instances pad to two k-steps (256 spins): the generic tile's rounds are two
+// k-steps at two workgroups per CU, and a remainder of two k-steps runs unpipelined at one
+constexpr int kBatchRowPad = 2 * kKS;
 
 // FIX16: 16-bit fixed point, q = rint(x 2^14) split into int8 hi/lo planes
 // (q = 256 hi + lo), J in int8, two int8 MFMA passes with exact int32 accumulation.

@@ -12,7 +12,9 @@ from paper_2508_17655_amd import instances
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [64, 200, 333, 700, 1500, 2600]  # ragged; padded sizes 512 .. 3072
+# ragged; padded to 256 spins: 256 .. 2816, i.e. 2 to 22 k-steps, several of them not a
+# multiple of the one-workgroup-per-CU variant's 4-k-step rounds (its unpipelined remainder)
+SIZES = [64, 200, 333, 700, 1500, 2600]
 R = 128
 
 
@@ -107,7 +109,7 @@ def test_every_tile_shape_gives_the_same_bits():
     ref = None
     for rows in (64, 128, 256):
         for k, n in enumerate(SIZES):
-            np_ = (n + 511) // 512 * 512
+            np_ = (n + 255) // 256 * 256
             b.set(k, gsb.GSB_BATCH_TILE_ROWS, rows if np_ // rows <= cap else 0)
         b.run("gbsb", A=A, steps=M, seed=seed)
         got = [b.state(k) for k in range(len(SIZES))]
