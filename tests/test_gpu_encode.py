@@ -56,6 +56,27 @@ def test_fp8_every_value_in_unit_interval(orc):
     assert total == 2 * (ONE + 1)
 
 
+def test_sign_operand_every_value_in_unit_interval(orc):
+    """The sign operand of dSB/GdSB (+1 or -1 in E4M3, s(x) = +1 for x >= 0, -0.0 included,
+    reading R2) for every binary32 |x| <= 1: every negative denormal must give -1 and -0.0
+    must give +1, whatever the encoder computes the sign bit from."""
+    import torch
+    gsb = _gsb()
+    say("case encode sign operand exhaustive |x| <= 1")
+    total = 0
+    for sign, xh in _chunks():
+        x = torch.from_numpy(xh).cuda()
+        got = gsb.encode_operand(x, gsb.GSB_PREC_FP8, discrete=True).cpu().numpy()
+        s = orc.operand(xh, orc.FORM_EXACT, discrete=True)
+        ref = np.where(s > 0, 0x38, 0xB8).astype(np.uint8)
+        bad = np.flatnonzero(got != ref)
+        assert bad.size == 0, (f"x = {xh[bad[0]]!r} ({xh[bad[0]:bad[0]+1].view(np.uint32)[0]:#010x}): "
+                               f"device {got[bad[0]]:#04x}, oracle {ref[bad[0]]:#04x}; {bad.size} in chunk")
+        total += xh.size
+    say(f"sign operand: {total} values equal to the oracle's s(x)")
+    assert total == 2 * (ONE + 1)
+
+
 def test_fix16_every_value_in_unit_interval(orc):
     import torch
     gsb = _gsb()
