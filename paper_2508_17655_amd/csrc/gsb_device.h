@@ -75,8 +75,9 @@ __device__ __forceinline__ bool group_sync(unsigned* ctr, unsigned target, int l
 // Q holds, per (16-replica block rb, 128-spin k-step kc), the operand bytes in exactly the
 // order the MFMA B operand is held in a wavefront's lanes, so a fragment is one coalesced
 // 1 KiB load per VGPR quad:
-//   FP8   : 2048 B = [half 2][lane 64][16 B];  lane = r%16 + 16*(kk/32),
-//           byte 16*half + b  <->  kk = 32*(lane/16) + 16*half + b            (16x16x128)
+//   FP8   : 2048 B = [half 2][lane 64][16 B];  lane = r%16 + 16*((kk/4)%4),
+//           half kk/64, byte 4*((kk/16)%4) + kk%4                            (16x16x128;
+//           a permutation of the spins within the k-step, see fp8_elem_offset)
 //   BF16  : 32x32x16 bf16 MFMA.  Per (32-replica block, k-step): 8 KiB per plane =
 //           [sixteenth 8][lane 64][8 bf16]; lane = r%32 + 32*((kk%16)/8),
 //           kk = 16*sixteenth + 8*(lane/32) + e; plane 0 holds hi, plane 1 lo.
@@ -87,7 +88,8 @@ __device__ __forceinline__ bool group_sync(unsigned* ctr, unsigned target, int l
 //           kk = 32*quarter + 16*(lane/32) + b; plane 0 holds hi, plane 1 lo of
 //           q = rint(x 2^14) = 256 hi + lo, hi in [-64, 64], lo in [-128, 127].  J: the same
 //           per (32-row tile, k-step), rows in place of replicas.
-// (kk = k mod 128.)  J uses the same layouts with the row i in place of the replica r.
+// (kk = k mod 128.)  J uses the same layouts with the row i in place of the replica r
+// (FP4 J of the FP8 product: see fp4_pair_kk).
 // store_operand receives the 16x16 tile origin (ibase, rcol) of the lane's elements, or
 // for the 32x32 layouts (BF16, FIX16) the lane's own first element (row ibase,
 // ibase % 4 == 0, column rcol).
