@@ -13,18 +13,18 @@
 // The matrix cores and the vector ALU of a SIMD execute instructions of different waves
 // at the same time, so the update of one column tile runs under the K loop of the other.
 //
-// Operand exchange.  Every operand word carries a tag of the step that wrote it, in bit 6
-// of its first byte (the E4M3 code of a value in [-1, 1] never sets that bit; the wall of
-// eq. (5) keeps x there).  Operand k (k = 0 at the launch's first step) sits in buffer
-// k % 2 with tag (k / 2) % 2, so a buffer holds either the operand a product wave wants or
-// the one two steps older, whose tag differs.  The update waves write the operand in
-// aligned 64-bit units, two words of one lane per store (the operand placement keeps a
-// lane's rows together), and an aligned 64-bit store is seen whole or not at all; each
-// product wave strips the tag of every word it loads, checks one word per unit and loads
-// again while any is stale (the sign operand of dSB and GdSB carries the tag in every
-// byte and is not stripped: tagged, its bytes are +-256 instead of +-1, which the MFMA's
-// E8M0 block scale of 2^-8 undoes exactly), and no group counter is needed between
-// steps.  The launch's first operand is behind the group counter (buffer 1 is cleared to
+// Operand exchange.  The update waves write the operand in aligned 64-bit units, two
+// words of one lane per store (the operand placement keeps a lane's rows together), and
+// an aligned 64-bit store is seen whole or not at all.  The first word of every unit
+// carries a tag of the step that wrote it, in bit 6 of its first byte (the E4M3 code of a
+// value in [-1, 1] never sets that bit; the wall of eq. (5) keeps x there).  Operand k
+// (k = 0 at the launch's first step) sits in buffer k % 2 with tag (k / 2) % 2, so a
+// buffer holds either the operand a product wave wants or the one two steps older, whose
+// tag differs.  Each product wave strips and checks the tagged word of every unit it
+// loads and loads again while any is stale (the sign operand of dSB and GdSB carries the
+// tag in every byte of every word and is not stripped: tagged, its bytes are +-256
+// instead of +-1, which the MFMA's E8M0 block scale of 2^-8 undoes exactly), and no group
+// counter is needed between steps.  The launch's first operand is behind the group counter (buffer 1 is cleared to
 // the stale tag under the same counter).  Where the group spans XCDs, whose L2 caches are
 // not coherent with each other, every step also goes through the group counter with
 // agent-scope fences, and the product waves meet in LDS where one of them polls it.
@@ -199,9 +199,9 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
       return true;
     };
     // strip the step tag from fragments and report (for the whole wave) whether any of
-    // their words was stale: pat is the expected tag, cmask 0x40 (or 0: no check).  The
+    // their units was stale: pat is the expected tag, cmask 0x40 (or 0: no check).  The
     // update waves write the operand in aligned 64-bit units (two words of one lane, one
-    // store), so one word of each unit tells its step: words 0, 2, 4, 6 of the fragment.
+    // store), so the first word of each unit tells its step: words 0, 2, 4, 6.
     // The sign product keeps its tags: there the tag is in every byte of a word, a tagged
     // +-1 byte is +-256 exactly, and the MFMA's block scale of the operand (2^-8 for a
     // tagged operand) takes the factor back exactly, so the words are only checked.
@@ -212,10 +212,11 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
         o = __builtin_amdgcn_bitop3_b32((unsigned)b[0], (unsigned)b[2], pat, 0x7E) |
             __builtin_amdgcn_bitop3_b32((unsigned)b[4], (unsigned)b[6], pat, 0x7E);
       } else {
+        // the E4M3 operand's tag is in the first word of each unit only
 #pragma unroll
-        for (int d = 0; d < 8; ++d) {
+        for (int d = 0; d < 8; d += 2) {
           b[d] ^= (int)pat;
-          if (d % 2 == 0) o |= (unsigned)b[d];
+          o |= (unsigned)b[d];
         }
       }
       return o;
@@ -455,7 +456,9 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
     // each aligned 64-bit unit (an aligned 64-bit store is seen whole or not at all)
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const v2u wd{encode_fp8x4<DISC>(xs[sub][2 * h], tag), encode_fp8x4<DISC>(xs[sub][2 * h + 1], tag)};
+      // the E4M3 operand carries the tag in the unit's first word only (the product waves
+      // strip and check that word); the sign operand in every byte (its block scale)
+      const v2u wd{encode_fp8x4<DISC>(xs[sub][2 * h], tag), encode_fp8x4<DISC>(xs[sub][2 * h + 1], DISC ? tag : 0u)};
       __builtin_amdgcn_raw_buffer_store_b64(wd, qw, qoff[sub] + 8 * h, qbase, 0);
     }
   };
@@ -472,7 +475,7 @@ __global__ void __launch_bounds__(kWsThreads, 1) k_steps_ws(StepArgs a) {
         store_operand<kFormFP8, DISC>(a.q, a.q_buf_bytes, NKS, row0 + rt * 16, col0 + sub * 16, lane,
                                       xs[sub][rt]);
         store_operand<kFormFP8, DISC>(a.q + a.q_buf_bytes, a.q_buf_bytes, NKS, row0 + rt * 16, col0 + sub * 16,
-                                      lane, xs[sub][rt], kTag);
+                                      lane, xs[sub][rt], DISC || rt % 2 == 0 ? kTag : 0u);
       }
     arrive(ctr0);
     arrive(ctr1);
