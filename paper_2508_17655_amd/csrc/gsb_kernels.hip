@@ -551,8 +551,18 @@ __device__ __forceinline__ void steps_tile(const StepArgs& a, int g, int mb, int
           ys[rt][ct][v] = hit ? 0.0f : yn;
           ps[rt][ct][v] = pn;
         }
-        store_q(qnext, rt, ct, xs[rt][ct]);
+        if constexpr (FORM != kFormFP8) store_q(qnext, rt, ct, xs[rt][ct]);
       }
+    if constexpr (FORM == kFormFP8) {
+      // the FP8 placement keeps a lane's four row tiles of a column tile in 16 contiguous,
+      // aligned bytes (row0 is a multiple of 64): one 16-byte store per column tile
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        const v4u w{encode_fp8x4<DISC>(xs[0][ct]), encode_fp8x4<DISC>(xs[1][ct]), encode_fp8x4<DISC>(xs[2][ct]),
+                    encode_fp8x4<DISC>(xs[3][ct])};
+        *reinterpret_cast<v4u*>(qnext + fp8_operand_offset(nks, row0, col0 + ct * 16, lane)) = w;
+      }
+    }
     }
     alive = group_sync(ctr, (unsigned)((s + 2) * a.nb), local, abort_flag, a.status, &s_flag);
   }
