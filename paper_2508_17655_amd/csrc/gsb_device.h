@@ -161,7 +161,7 @@ __device__ __forceinline__ void encode_fix16x4(const float xv[4], unsigned& wh, 
 // so that the sixteen spins 64 h + 16 t + 4 L + v (t, v < 4) of one replica -- the four
 // row tiles t of lane L of a 16x16 MFMA result, rows 4 L + v -- are one lane's 16
 // contiguous bytes, which the lane that computed them can store with wide stores.
-__device__ __forceinline__ size_t fp8_elem_offset(int nks, int r, int k) {
+__host__ __device__ __forceinline__ size_t fp8_elem_offset(int nks, int r, int k) {
   const int kk = k & 127;
   const int lanep = (r & 15) + 16 * ((kk >> 2) & 3);
   return ((size_t)((r >> 4) * nks + (k >> 7)) * 2 + (kk >> 6)) * 1024 + lanep * 16 + (((kk >> 4) & 3) << 2) +
@@ -169,7 +169,7 @@ __device__ __forceinline__ size_t fp8_elem_offset(int nks, int r, int k) {
 }
 // Offset of the FP8 word of a lane's four rows (16x16 tile origin ibase, rcol; rows
 // ibase + 4 (lane / 16) + v, replica rcol + lane mod 16): bytes v of one word.
-__device__ __forceinline__ size_t fp8_operand_offset(int nks, int ibase, int rcol, int lane) {
+__host__ __device__ __forceinline__ size_t fp8_operand_offset(int nks, int ibase, int rcol, int lane) {
   return fp8_elem_offset(nks, rcol + (lane & 15), ibase + 4 * (lane >> 4));
 }
 
@@ -225,7 +225,7 @@ __device__ __forceinline__ void store_operand(uint8_t* qbuf, size_t plane_bytes,
 // of a row tile, 32 per group) multiplies MFMA k index p of the operand, which is FP8 byte
 // j = p mod 16 of lane group (p mod 64) / 16 in half p / 64; the spin there is the one the
 // operand placement (fp8_elem_offset) puts at that byte.
-__device__ __forceinline__ int fp4_pair_kk(int p) {
+__host__ __device__ __forceinline__ int fp4_pair_kk(int p) {
   return 64 * (p >> 6) + 16 * ((p >> 2) & 3) + 4 * ((p >> 4) & 3) + (p & 3);
 }
 __device__ __forceinline__ unsigned fp4_code(float v) {  // exact for 0 and +-1
